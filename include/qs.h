@@ -1,0 +1,193 @@
+/*
+ * qs.h -- C ABI of libqs, a single-GPU (MI355X, gfx950) state-vector
+ * simulator for linear-ramp QAOA (LR-QAOA) circuits on weighted complete
+ * graphs (arXiv:2604.26423, Sec. II-B).
+ *
+ * The circuit: |+>^n (a Hadamard on every qubit), then p layers, each the
+ * cost unitary of eq. (2) followed by the mixer of eq. (3).  The library
+ * works in gate angles, which makes it independent of the sign and scale
+ * convention used for (gamma_k, beta_k):
+ *   layer k = [prod_{i<j} RZZ(theta_zz[k] * w_ij)] then [prod_q RX(theta_x[k])]
+ *   RZZ(t) = exp(-i t/2 Z(x)Z),   RX(t) = exp(-i t/2 X).
+ * The paper's unitaries exp(-i gamma H_C) and exp(+i beta sum_q X_q) are
+ * theta_zz = 2 gamma, theta_x = -2 beta.
+ *
+ * Conventions shared by every call
+ *   - Qubit q is bit q of the amplitude index; amplitude x of an n-qubit
+ *     state sits at element x of a contiguous array of 2^n complex numbers
+ *     (interleaved re, im; float for QS_C64, double for QS_C128).
+ *   - Edge weights are integers in tenths (w_ij = w_t / 10), listed for
+ *     pairs i<j in lexicographic order (0,1),(0,2),...,(0,n-1),(1,2),...
+ *   - The cost diagonal is int32 C_t[x] = 10 * C(x), C(x) the cut value of
+ *     eq. (6); W_t = sum of the weights in tenths.  H_C(x) = (W_t - 2 C_t[x])/10.
+ *   - Every function returns a qs_status; QS_OK is 0.  On any other value
+ *     qs_last_error() returns a message for the calling thread.  No C++
+ *     exception, abort or exit crosses this interface.  Arguments are
+ *     checked before any GPU work is queued.
+ *   - Device pointers are HIP device pointers on the current device.  All
+ *     GPU work of a state is queued on the HIP stream given to qs_alloc;
+ *     functions that return host values synchronise that stream first.
+ *   - A state handle is not thread-safe: calls on one handle must not
+ *     overlap.  Different handles are independent.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QS_OK = 0,
+    QS_ERR_ARG = 1,   /* invalid argument (null pointer, size, range of n, p, ...) */
+    QS_ERR_OOM = 2,   /* device allocation failed */
+    QS_ERR_HIP = 3,   /* any other HIP runtime error; message has the HIP string */
+    QS_ERR_RANGE = 4, /* an integer result would not fit (e.g. W_t >= 2^31) */
+    QS_ERR_STATE = 5  /* state content unusable (e.g. zero norm when sampling) */
+} qs_status;
+
+typedef enum { QS_C64 = 0, QS_C128 = 1 } qs_prec;
+
+/* Largest supported qubit counts: 2^34 complex64 = 128 GiB, 2^33 complex128 = 128 GiB. */
+#define QS_MAX_QUBITS_C64 34
+#define QS_MAX_QUBITS_C128 33
+
+typedef struct qs_state_s *qs_state;
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *qs_last_error(void);
+
+/* Library version string. */
+const char *qs_version(void);
+
+/* Bytes of an n-qubit state: 2^n * 8 (QS_C64) or 2^n * 16 (QS_C128);
+ * 0 if n or prec is out of range.  (Sec. II-E: FP32 needs 2^(N+3) bytes.) */
+size_t qs_state_bytes(int n, int prec);
+
+/*
+ * Create a state handle for n qubits (1 <= n <= QS_MAX_QUBITS_*).
+ * dev_buf: NULL -> the library allocates 2^n amplitudes and frees them in
+ *          qs_free; otherwise a caller-owned device buffer of buf_bytes >=
+ *          qs_state_bytes(n, prec), 256-byte aligned, that must outlive the
+ *          handle.
+ * hip_stream: hipStream_t for all work on this state (NULL = null stream).
+ * The amplitudes are not initialised.  The handle also owns grow-only
+ * device scratch for reductions and sampling, freed by qs_free.
+ */
+qs_status qs_alloc(int n, int prec, void *dev_buf, size_t buf_bytes, void *hip_stream,
+                   qs_state *out);
+
+/* Release the handle, its scratch and (if library-owned) its amplitudes. */
+qs_status qs_free(qs_state s);
+
+/* Device pointer of the amplitudes (2^n complex numbers). */
+qs_status qs_state_ptr(qs_state s, void **dev_ptr);
+
+/* Change the stream used for later work on this state. */
+qs_status qs_set_stream(qs_state s, void *hip_stream);
+
+/* |+>^n: every amplitude 2^(-n/2) (Sec. II-B, initial state). */
+qs_status qs_init_plus(qs_state s);
+
+/*
+ * Cost diagonal of eq. (6) on the device.
+ * w_tenths: host array of n(n-1)/2 weights in tenths, each in [0, 2^20).
+ * diag_dev: caller-owned device array of 2^n int32, written in full.
+ * w_total_tenths (out, host, nullable): W_t.
+ * cmax_tenths (out, host, nullable): max_x C_t[x] = 10 * C(x*) of eq. (5).
+ * hip_stream: stream to use.  Synchronises it when cmax_tenths is non-null.
+ * Errors: QS_ERR_ARG (n outside 1..34, null pointers, negative or too large
+ * weight), QS_ERR_RANGE (W_t >= 2^31).
+ */
+qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev,
+                           int64_t *w_total_tenths, int32_t *cmax_tenths, void *hip_stream);
+
+/*
+ * One cost layer, eq. (2): prod_{i<j} RZZ(theta_zz * w_ij), applied as the
+ * diagonal phase exp(-i theta_zz (W_t - 2 C_t[x]) / 20) on every amplitude.
+ * The phase argument is reduced modulo 2 pi in FP64.
+ */
+qs_status qs_apply_cost_layer(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths,
+                              double theta_zz);
+
+/* One mixer layer, eq. (3): RX(theta_x) on every qubit. */
+qs_status qs_apply_mixer(qs_state s, double theta_x);
+
+/*
+ * The whole circuit: |+>^n, then layers k = 0..p-1 with angles
+ * theta_zz[k], theta_x[k] (host arrays of length p; p >= 0).  Same result
+ * as qs_init_plus followed by p pairs of qs_apply_cost_layer and
+ * qs_apply_mixer, computed with fewer passes over memory.
+ * exp_c, norm (host, nullable): when exp_c is non-null the readout of
+ * qs_expect is fused into the last pass and returned (synchronises).
+ */
+qs_status qs_forward(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                     const double *theta_zz, const double *theta_x, double *exp_c, double *norm);
+
+/*
+ * <C> and the norm, FP64 reductions in a fixed order (run-to-run identical):
+ *   norm = sum_x |a_x|^2,  exp_c = (sum_x |a_x|^2 C_t[x] / 10) / norm.
+ * exp_c is the expected cut (eq. 5 with exact probabilities), in weight units.
+ */
+qs_status qs_expect(qs_state s, const int32_t *diag_dev, double *exp_c, double *norm);
+
+/*
+ * Measurement shots (Sec. II-B), reproducible bit for bit:
+ *   P(x) = re^2 + im^2 in FP64 (single precision promoted first, no fused
+ *   multiply-add), q(x) = floor(P(x) 2^62) as uint64, F(x) = sum_{y<=x} q(y),
+ *   T = F(2^n - 1); shot s uses r = word 0 of Philox4x64-10 with counter
+ *   (s, 0, 0, 0) and key (seed, 0), u = floor(r T / 2^64), and returns
+ *   x_s = min { x : F(x) > u }.
+ * out: shots uint64 values, on the device if out_on_device, else on the host.
+ * Errors: QS_ERR_ARG (shots < 0, null out), QS_ERR_STATE (T = 0 or the
+ * state norm is 4 or more, where q would overflow).
+ */
+qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int out_on_device);
+
+/*
+ * Forward circuit plus the adjoint (reverse state-vector) gradient of
+ * E = <psi_p| C |psi_p> / <psi_p|psi_p> with C(x) = C_t[x] / 10:
+ *   d_theta_zz[k] = dE/dtheta_zz[k],  d_theta_x[k] = dE/dtheta_x[k]
+ * (host arrays of length p >= 1; exp_c receives E).  The reverse sweep
+ * undoes every layer on the state and on the adjoint vector (no stored
+ * checkpoints), so it needs exactly two state vectors for any p.
+ * lambda_buf: caller-owned device buffer of lambda_bytes >= qs_state_bytes
+ * for the adjoint vector, or NULL to let the library allocate it for the call.
+ * On return the state holds |+>^n up to rounding (it has been uncomputed).
+ * Needs n >= 2.  Synchronises.
+ */
+qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                          const double *theta_zz, const double *theta_x, void *lambda_buf,
+                          size_t lambda_bytes, double *exp_c, double *d_theta_zz,
+                          double *d_theta_x);
+
+/*
+ * Per-kernel timing.  While enabled, HIP events bracket every kernel the
+ * handle launches.  qs_profile_read synchronises and reports, for one kernel
+ * kind, the launch count, the summed event time and the summed algorithmic
+ * bytes (the bytes each launch must move at minimum).  Enabling clears.
+ */
+typedef enum {
+    QS_KIND_PASS = 0,        /* mixer pass kernels (state read + write) */
+    QS_KIND_PASS_PHASE = 1,  /* mixer pass kernels that also apply a cost phase */
+    QS_KIND_ADJOINT = 2,     /* reverse-sweep kernels (two vectors) */
+    QS_KIND_EXPECT = 3,      /* stand-alone <C>/norm readout */
+    QS_KIND_SAMPLE = 4,      /* sampling kernels */
+    QS_KIND_ELEMENTWISE = 5, /* init and stand-alone cost-layer kernels */
+    QS_KIND_REDUCE = 6,      /* small reductions of per-workgroup partials */
+    QS_KIND_SMALL = 7,       /* single-workgroup kernels for states of <= 8192 amplitudes */
+    QS_KIND_COUNT = 8
+} qs_kernel_kind;
+
+qs_status qs_profile(qs_state s, int enable);
+qs_status qs_profile_read(qs_state s, int kind, int64_t *launches, double *total_ms,
+                          double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

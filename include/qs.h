@@ -156,8 +156,9 @@ qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int
  * checkpoints), so it needs exactly two state vectors for any p.
  * lambda_buf: caller-owned device buffer of lambda_bytes >= qs_state_bytes
  * for the adjoint vector, or NULL to let the library allocate it for the call.
- * On return the state holds |+>^n up to rounding (it has been uncomputed).
- * Needs n >= 2.  Synchronises.
+ * On return the state buffer holds an intermediate of the reverse sweep (its
+ * contents are unspecified); qs_forward recomputes psi_p.  The adjoint buffer
+ * is overwritten too.  Needs n >= 2.  Synchronises.
  */
 qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
                           const double *theta_zz, const double *theta_x, void *lambda_buf,

@@ -1,0 +1,35 @@
+/*
+ * qs_debug.h -- host-only diagnostics of libqs.  Nothing here touches a GPU.
+ */
+#ifndef QS_DEBUG_H
+#define QS_DEBUG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/*
+ * Check, on the host, the pass plan that qs_forward / qs_adjoint_grad use for
+ * an n-qubit state of precision prec and p layers:
+ *   - the passes' target qubits partition 0..n-1;
+ *   - every register window lies inside the tile and the windows of each
+ *     butterfly stage cover the pass's targets;
+ *   - each window layout is a bijection of the tile, and the fast and general
+ *     register-to-memory index maps agree;
+ *   - the tiles of each pass cover every amplitude index exactly once and stay
+ *     below 2^n (exhaustive for n <= 24, sampled workgroups above);
+ *   - the fused kernel sequence applies, for every layer k, the cost phase once
+ *     after all of layer k-1's mixer and before any of layer k's, and every
+ *     pass's mixer once per layer.
+ * Returns 0 when every check holds, else 1 with a description in msg
+ * (msg may be NULL).  n outside 1..34 or prec not 0/1 returns 2.
+ */
+int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_DEBUG_H */

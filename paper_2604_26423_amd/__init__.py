@@ -1,0 +1,11 @@
+"""MI355X (gfx950) state-vector simulation of LR-QAOA circuits (arXiv:2604.26423).
+
+The compute path is libqs.so (HIP kernels behind the C ABI of include/qs.h);
+``qs`` is its thin binding and ``lrqaoa`` the schedule / simulator layer.
+Nothing here falls back to a CPU implementation: without the built library
+every call raises.
+"""
+from . import qs  # noqa: F401
+from .lrqaoa import Simulator, expect_c, linear_ramp, to_gate_angles, gate_grad_to_schedule  # noqa: F401
+
+__all__ = ["qs", "Simulator", "expect_c", "linear_ramp", "to_gate_angles", "gate_grad_to_schedule"]

@@ -1,0 +1,156 @@
+// Device-side building blocks shared by the kernels of libqs (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace qs {
+
+template <typename V> struct Real;
+template <> struct Real<float2> { using T = float; };
+template <> struct Real<double2> { using T = double; };
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b)
+{
+    return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// FP64 phase argument reduced to (-pi, pi].
+__device__ __forceinline__ double reduce_2pi(double a)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    return a - two_pi * rint(a / two_pi);
+}
+
+// exp(i a) for an FP64 argument, rounded to the state precision.
+template <typename V> __device__ __forceinline__ V expi(double a);
+template <> __device__ __forceinline__ float2 expi<float2>(double a)
+{
+    double s, c;
+    sincos(reduce_2pi(a), &s, &c);
+    return float2{(float)c, (float)s};
+}
+template <> __device__ __forceinline__ double2 expi<double2>(double a)
+{
+    double s, c;
+    sincos(reduce_2pi(a), &s, &c);
+    return double2{c, s};
+}
+
+// RX(theta) on a pair (a0 = bit clear, a1 = bit set), c = cos(theta/2), s = sin(theta/2):
+//   a0' = c a0 - i s a1,  a1' = -i s a0 + c a1.
+template <typename V, typename R>
+__device__ __forceinline__ void rx_pair(V &a0, V &a1, R c, R s)
+{
+    V b0{c * a0.x + s * a1.y, c * a0.y - s * a1.x};
+    V b1{c * a1.x + s * a0.y, c * a1.y - s * a0.x};
+    a0 = b0;
+    a1 = b1;
+}
+
+// Butterflies on register bit K of an array of NR amplitudes.
+template <int K, typename V, int NR, typename R>
+__device__ __forceinline__ void rx_reg_bit(V (&v)[NR], R c, R s)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) rx_pair(v[r], v[r | (1 << K)], c, s);
+}
+
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rx_reg_mask(V (&v)[NR], uint32_t mask, R c, R s)
+{
+    if (mask & 1u) rx_reg_bit<0>(v, c, s);
+    if (mask & 2u) rx_reg_bit<1>(v, c, s);
+    if (mask & 4u) rx_reg_bit<2>(v, c, s);
+    if (mask & 8u) rx_reg_bit<3>(v, c, s);
+    if constexpr (NR >= 32) { if (mask & 16u) rx_reg_bit<4>(v, c, s); }
+    if constexpr (NR >= 64) { if (mask & 32u) rx_reg_bit<5>(v, c, s); }
+}
+
+// Im <lam| X_q |psi> restricted to the pairs held in registers, for register bit K:
+// sum over pairs of Im(conj(l0) p1) + Im(conj(l1) p0), accumulated in FP64.
+template <int K, typename V, int NR>
+__device__ __forceinline__ double imx_reg_bit(const V (&l)[NR], const V (&p)[NR])
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) {
+            const V l0 = l[r], l1 = l[r | (1 << K)], p0 = p[r], p1 = p[r | (1 << K)];
+            acc += (double)l0.x * (double)p1.y - (double)l0.y * (double)p1.x;
+            acc += (double)l1.x * (double)p0.y - (double)l1.y * (double)p0.x;
+        }
+    return acc;
+}
+
+template <typename V, int NR>
+__device__ __forceinline__ double imx_reg_mask(const V (&l)[NR], const V (&p)[NR], uint32_t mask)
+{
+    double acc = 0.0;
+    if (mask & 1u) acc += imx_reg_bit<0>(l, p);
+    if (mask & 2u) acc += imx_reg_bit<1>(l, p);
+    if (mask & 4u) acc += imx_reg_bit<2>(l, p);
+    if (mask & 8u) acc += imx_reg_bit<3>(l, p);
+    if constexpr (NR >= 32) { if (mask & 16u) acc += imx_reg_bit<4>(l, p); }
+    if constexpr (NR >= 64) { if (mask & 32u) acc += imx_reg_bit<5>(l, p); }
+    return acc;
+}
+
+// LDS address of tile element e: one pad element every 32 to spread banks.
+__device__ __forceinline__ int lds_index(int e) { return e + (e >> 5); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
+// XCD works on a contiguous range of tiles (neighbouring tiles share L2 lines
+// of the cost diagonal and TLB pages).
+__device__ __forceinline__ int64_t xcd_tile(int remap)
+{
+    const int64_t b = blockIdx.x, g = gridDim.x;
+    if (!remap) return b;
+    return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// Move the NR amplitudes of every thread from layout `from` to layout `to`
+// through LDS.  Leading barrier: earlier LDS reads of this buffer are done.
+template <typename V, int NR>
+__device__ __forceinline__ void exchange(V (&v)[NR], V *lds, int from, int to, int tid, int rb)
+{
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) lds[lds_index(win_elem(r, tid, from, rb))] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = lds[lds_index(win_elem(r, tid, to, rb))];
+}
+
+// Deterministic workgroup sum of NV doubles (fixed shuffle tree, then waves in
+// order).  Result valid in thread 0.  `red` holds NV * (blockDim/64) doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&x)[NV], double *red, int tid, int nthreads)
+{
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x[k] += __shfl_xor(x[k], off, 64);
+    }
+    const int wave = tid >> 6, lane = tid & 63, nw = nthreads >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave * NV + k] = x[k];
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w * NV + k];
+            x[k] = s;
+        }
+    }
+}
+
+}  // namespace qs

@@ -1,0 +1,153 @@
+// Internal declarations shared by the kernel translation units and the C ABI
+// layer of libqs.  Not installed; the public interface is include/qs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+constexpr int kThreads = 256;         // threads per workgroup of the tile kernels
+constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
+constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
+constexpr int kMaxWindows = 4;        // register windows per butterfly stage
+constexpr int kPhaseTableMaxW = 8192; // W_t below this: two-level phase table in LDS
+constexpr int kSmallMaxLayers = 32;   // layers per launch of the single-workgroup kernel
+constexpr int kSlots = 4;             // FP64 partial sums per workgroup
+
+inline int tile_bits(int prec) { return prec == 0 ? kTileBitsC64 : kTileBitsC128; }
+
+// Butterfly stage: a sequence of register windows.  In window s a thread's
+// register index r holds tile bits [s, s + RB); its thread index fills the
+// remaining tile bits in order.  s = 8 is the "natural" layout.
+struct WinSeq {
+    int cnt;
+    int s[kMaxWindows];
+};
+
+// One tile pass over the state.  A tile is 2^T amplitudes: tile bits
+// [0, c) are the "carrier" bits, equal to global bits [0, c) (contiguous
+// runs in memory), and tile bits [c, T) are the target qubits
+// [q0, q0 + T - c).  The workgroup index supplies the other global bits.
+struct PassProg {
+    void *psi;            // state (float2 / double2)
+    void *lam;            // adjoint vector (reverse kernels only)
+    const int32_t *diag;  // cost diagonal in tenths
+    double *partials;     // kSlots doubles per workgroup
+    int n, c, q0;
+    uint32_t targets;     // mask of tile bits that are gate targets: [c, T)
+    int xcd_remap;        // map consecutive tiles to one XCD
+    int init;             // start from |+>^n instead of loading
+    int has_pre, has_phase, has_post, readout;
+    int load_win;         // layout of the first global access
+    WinSeq A, B;          // windows of the pre and post butterfly stages
+    double pre_c, pre_s;  // RX(theta_pre): cos, sin of theta/2
+    double post_c, post_s;
+    double theta_zz;      // phase angle of the fused cost layer
+    int64_t W;            // W_t
+    int phase_table;      // 1: two-level table, 0: per-element FP64 argument
+    double amp0;          // 2^(-n/2)
+};
+
+// ---- index maps of a tile pass (host and device) ----
+
+// Tile element held by (register r, thread tid) in the layout of window s.
+__host__ __device__ __forceinline__ int win_elem(int r, int tid, int s, int rb)
+{
+    return (tid & ((1 << s) - 1)) | (r << s) | ((tid >> s) << (s + rb));
+}
+
+// Global amplitude index of tile element e.
+__host__ __device__ __forceinline__ int64_t tile_gidx(int e, int64_t base, int c, int q0)
+{
+    return base | (int64_t)(e & ((1 << c) - 1)) | ((int64_t)(e >> c) << q0);
+}
+
+// Workgroup index -> global bits outside the tile.  Bits [c, q0) come from the
+// low part of w, bits [q0 + m, n) from the high part (m = T - c).
+__host__ __device__ __forceinline__ int64_t tile_base(int64_t w, int c, int q0, int m)
+{
+    const int nlow = q0 - c;
+    const int64_t wl = w & (((int64_t)1 << nlow) - 1);
+    const int64_t wh = w >> nlow;
+    return (wl << c) | (wh << (q0 + m));
+}
+
+// Global index of (register r, thread) in window s.  When the window starts at
+// or above the carrier bits (s >= c) its register bits are contiguous global
+// bits and the index is the thread's r = 0 element plus r << sh; otherwise
+// (passes with more than 8 carrier bits) each register bit is mapped apart.
+struct Addr {
+    int64_t tg;
+    int sh, s, c, q0;
+    bool fast;
+    __host__ __device__ __forceinline__ int64_t fast_idx(int r) const { return tg + ((int64_t)r << sh); }
+    __host__ __device__ __forceinline__ int64_t slow_idx(int r) const
+    {
+        const int e = r << s;
+        return tg + (int64_t)(e & ((1 << c) - 1)) + ((int64_t)(e >> c) << q0);
+    }
+};
+
+__host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_t base, int c, int q0)
+{
+    return Addr{tile_gidx(win_elem(0, tid, s, rb), base, c, q0), q0 + s - c, s, c, q0, s >= c};
+}
+
+// Host-side launchers (one per kernel family); all return hipError_t.
+hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
+hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid,
+                               hipStream_t st);
+
+// Single-workgroup kernels for n <= T: a chunk of up to kSmallMaxLayers layers.
+struct SmallProg {
+    void *psi;
+    void *lam;
+    const int32_t *diag;
+    double *out;          // readout / gradient accumulators (device)
+    int n;
+    int init, readout;
+    int nlayers;
+    int64_t W;
+    double tzz[kSmallMaxLayers];
+    double tx[kSmallMaxLayers];
+    int do_phase[kSmallMaxLayers];
+    int do_mixer[kSmallMaxLayers];
+    int layer0;           // index of the first layer of the chunk (gradient slots)
+    int ptotal;           // total layers of the circuit (gradient slot layout)
+    int turnaround;       // adjoint: build lambda = C psi from the loaded psi first
+    int store;            // adjoint: write psi and lambda back
+    double amp0;          // 2^(-n/2)
+};
+hipError_t launch_small_forward(int prec, const SmallProg &sp, hipStream_t st);
+hipError_t launch_small_adjoint(int prec, const SmallProg &sp, hipStream_t st);
+
+// Elementwise and readout kernels.
+hipError_t launch_init_plus(int prec, void *psi, int n, hipStream_t st);
+hipError_t launch_cost_layer(int prec, void *psi, const int32_t *diag, int n, int64_t W,
+                             double theta, hipStream_t st);
+hipError_t launch_expect(int prec, const void *psi, const int32_t *diag, int n,
+                         double *partials, int64_t *nblocks, hipStream_t st);
+// Fixed-order reduction of kSlots-wide partials into dst[map[k]] (+= if accumulate).
+hipError_t launch_reduce(const double *partials, int64_t count, double *tmp, double *dst,
+                         const int *map, int accumulate, hipStream_t st);
+int64_t reduce_tmp_doubles(int64_t count);
+
+// Cost diagonal.
+hipError_t launch_cost_diagonal(int n, const int32_t *wmat_dev, int32_t *diag, int32_t *low_table,
+                                int32_t *wg_max, int32_t *tmp_max, int32_t *cmax_dev,
+                                hipStream_t st);
+int64_t diag_wg_count(int n);
+
+// Sampling.
+struct SampleBufs {
+    uint64_t *sub;     // in-block exclusive prefix of 64-amplitude sub-block sums
+    uint64_t *blk;     // in-chunk exclusive prefix of block sums
+    uint64_t *chunk;   // global exclusive prefix of chunk sums, then the total at [nchunks]
+    int32_t *flag;     // overflow / zero-total flag
+};
+void sample_sizes(int n, int64_t *nsub, int64_t *nblk, int64_t *nchunk);
+hipError_t launch_sample(int prec, const void *psi, int n, const SampleBufs &b, uint64_t seed,
+                         int64_t shots, uint64_t *out, hipStream_t st);
+
+}  // namespace qs

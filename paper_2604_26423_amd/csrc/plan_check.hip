@@ -1,0 +1,188 @@
+// Host-only verification of the pass plan (declared in include/qs_debug.h).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <random>
+#include <vector>
+
+#include "../../include/qs_debug.h"
+#include "plan.h"
+
+using namespace qs;
+
+namespace {
+
+struct Report {
+    char *msg;
+    size_t len;
+    int bad = 0;
+    int fail(const char *fmt, ...)
+    {
+        if (!bad && msg && len) {
+            va_list ap;
+            va_start(ap, fmt);
+            vsnprintf(msg, len, fmt, ap);
+            va_end(ap);
+        }
+        bad = 1;
+        return 1;
+    }
+};
+
+uint32_t window_mask(int s, int rb) { return ((1u << rb) - 1u) << s; }
+
+int check_windows(Report &R, const WinSeq &w, uint32_t targets, int T, const char *what)
+{
+    const int rb = T - 8;
+    if (w.cnt < 1 || w.cnt > kMaxWindows) return R.fail("%s: %d windows", what, w.cnt);
+    uint32_t cov = 0;
+    for (int i = 0; i < w.cnt; ++i) {
+        if (w.s[i] < 0 || w.s[i] + rb > T) return R.fail("%s: window %d starts at %d", what, i, w.s[i]);
+        cov |= window_mask(w.s[i], rb);
+    }
+    if ((cov & targets) != targets) return R.fail("%s: windows miss targets (cover %x, targets %x)", what, cov, targets);
+    return 0;
+}
+
+int check_layout(Report &R, int s, int T)
+{
+    const int rb = T - 8, nr = 1 << rb;
+    std::vector<char> seen(1u << T, 0);
+    for (int tid = 0; tid < kThreads; ++tid)
+        for (int r = 0; r < nr; ++r) {
+            const int e = win_elem(r, tid, s, rb);
+            if (e < 0 || e >= (1 << T)) return R.fail("window %d: element %d out of the tile", s, e);
+            if (seen[e]++) return R.fail("window %d: element %d held twice", s, e);
+        }
+    return 0;
+}
+
+int check_tile_maps(Report &R, int n, int T, const PassGeom &g, const WinSeq *seqs, int nseq)
+{
+    const int rb = T - 8, nr = 1 << rb, m = T - g.c;
+    const int64_t grid = (int64_t)1 << (n - T), dim = (int64_t)1 << n;
+    // workgroups to visit: all of them for n <= 24, else a sample
+    std::vector<int64_t> ws;
+    if (n <= 24) {
+        for (int64_t w = 0; w < grid; ++w) ws.push_back(w);
+    } else {
+        std::mt19937_64 rng(12345);
+        ws = {0, 1, grid / 2, grid - 2, grid - 1};
+        for (int i = 0; i < 64; ++i) ws.push_back((int64_t)(rng() % (uint64_t)grid));
+    }
+    std::vector<uint8_t> seen(n <= 24 ? (size_t)dim : 0, 0);
+    for (int64_t w : ws) {
+        const int64_t base = tile_base(w, g.c, g.q0, m);
+        if (base < 0 || base >= dim) return R.fail("pass c=%d q0=%d: base of tile %lld out of range", g.c, g.q0, (long long)w);
+        std::vector<int64_t> idx;
+        for (int e = 0; e < (1 << T); ++e) {
+            const int64_t x = tile_gidx(e, base, g.c, g.q0);
+            if (x < 0 || x >= dim) return R.fail("pass c=%d q0=%d: index %lld out of range", g.c, g.q0, (long long)x);
+            if (n <= 24) {
+                if (seen[x]++) return R.fail("pass c=%d q0=%d: index %lld visited twice", g.c, g.q0, (long long)x);
+            }
+        }
+        // register-to-memory maps of every window this pass uses
+        for (int q = 0; q < nseq; ++q)
+            for (int i = 0; i < seqs[q].cnt; ++i) {
+                const int s = seqs[q].s[i];
+                for (int tid = 0; tid < kThreads; tid += 37) {
+                    const Addr a = win_addr(tid, s, rb, base, g.c, g.q0);
+                    for (int r = 0; r < nr; ++r) {
+                        const int64_t want = tile_gidx(win_elem(r, tid, s, rb), base, g.c, g.q0);
+                        if (a.slow_idx(r) != want) return R.fail("window %d: general index map wrong", s);
+                        if (a.fast && a.fast_idx(r) != want) return R.fail("window %d: fast index map wrong", s);
+                    }
+                }
+            }
+    }
+    if (n <= 24)
+        for (int64_t x = 0; x < dim; ++x)
+            if (seen[x] != 1) return R.fail("pass c=%d q0=%d: index %lld not visited", g.c, g.q0, (long long)x);
+    return 0;
+}
+
+int check_schedule(Report &R, int P, int p)
+{
+    // walk the kernels in order and track, per layer, how many passes of the
+    // mixer have run and whether the phase has run
+    const std::vector<KSpec> ks = forward_specs(P, p);
+    std::vector<int> phase_done(p, 0), mixer_count(p, 0);
+    std::vector<std::vector<int>> pass_seen(p, std::vector<int>(P, 0));
+    if (ks.empty() || !ks[0].init || ks[0].phase != 0) return R.fail("first kernel must start from |+> with phase 0");
+    for (size_t i = 0; i < ks.size(); ++i) {
+        const KSpec &k = ks[i];
+        if (i > 0 && k.init) return R.fail("kernel %zu re-initialises", i);
+        auto rx = [&](int L) -> int {
+            if (L < 0 || L >= p) return R.fail("kernel %zu: bad layer %d", i, L);
+            if (!phase_done[L]) return R.fail("layer %d mixer before its phase", L);
+            if (pass_seen[L][k.pass]++) return R.fail("layer %d: pass %d twice", L, k.pass);
+            ++mixer_count[L];
+            return 0;
+        };
+        if (k.pre >= 0 && rx(k.pre)) return 1;
+        if (k.phase >= 0) {
+            const int L = k.phase;
+            if (L > 0 && mixer_count[L - 1] != P) return R.fail("layer %d phase before layer %d mixer finished", L, L - 1);
+            if (phase_done[L]++) return R.fail("layer %d phase twice", L);
+        }
+        if (k.post >= 0 && rx(k.post)) return 1;
+        if (k.pre >= 0 && k.post >= 0 && k.post != k.pre + 1) return R.fail("kernel %zu mixes layers %d and %d", i, k.pre, k.post);
+    }
+    for (int L = 0; L < p; ++L)
+        if (!phase_done[L] || mixer_count[L] != P) return R.fail("layer %d incomplete", L);
+    if (ks.size() != (size_t)(p * (P - 1) + 1)) return R.fail("kernel count %zu", ks.size());
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len)
+{
+    if (msg && msg_len) msg[0] = 0;
+    if (n < 1 || n > 34 || (prec != 0 && prec != 1) || p < 1) return 2;
+    Report R{msg, msg_len};
+    const int T = tile_bits(prec);
+    if (n <= T) return 0;  // single-workgroup path
+    const std::vector<PassGeom> geo = plan_passes(n, prec);
+    // target qubits partition 0..n-1
+    std::vector<int> owner(n, -1);
+    for (size_t i = 0; i < geo.size(); ++i) {
+        const PassGeom &g = geo[i];
+        const int m = T - g.c;
+        if (g.c < 0 || g.c >= T) return R.fail("pass %zu: carrier bits %d", i, g.c);
+        if (g.targets != (((1u << T) - 1u) & ~((1u << g.c) - 1u))) return R.fail("pass %zu: target mask", i);
+        if (i == 0 && (g.c != 0 || g.q0 != 0)) return R.fail("first pass must be the low tile");
+        if (i > 0 && g.q0 < g.c) return R.fail("pass %zu: q0 below the carriers", i);
+        if (g.q0 + m > n) return R.fail("pass %zu: targets beyond n", i);
+        for (int q = g.q0; q < g.q0 + m; ++q) {
+            if (owner[q] >= 0) return R.fail("qubit %d in passes %d and %zu", q, owner[q], i);
+            owner[q] = (int)i;
+        }
+    }
+    for (int q = 0; q < n; ++q)
+        if (owner[q] < 0) return R.fail("qubit %d in no pass", q);
+    for (int s = 0; s + (T - 8) <= T; ++s)
+        if (check_layout(R, s, T)) return 1;
+    for (const PassGeom &g : geo) {
+        WinSeq seq[3];
+        seq[0] = plan_windows(8, g.targets, T);                    // single stage
+        seq[1] = plan_windows(8, g.targets, T);                    // pre stage
+        seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, T);  // post stage after pre
+        if (check_windows(R, seq[0], g.targets, T, "single stage")) return 1;
+        if (check_windows(R, seq[2], g.targets, T, "post stage")) return 1;
+        if (check_tile_maps(R, n, T, g, seq, 3)) return 1;
+    }
+    if (check_schedule(R, (int)geo.size(), p)) return 1;
+    // the XCD renumbering is a bijection whenever it is enabled (grid % 8 == 0)
+    const int64_t grid = (int64_t)1 << (n - T);
+    if (grid % 8 == 0 && grid <= (1 << 22)) {
+        std::vector<uint8_t> seen((size_t)grid, 0);
+        for (int64_t b = 0; b < grid; ++b) {
+            const int64_t w = (b & 7) * (grid >> 3) + (b >> 3);
+            if (w < 0 || w >= grid || seen[w]++) return R.fail("XCD renumbering is not a bijection");
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,199 @@
+"""LR-QAOA on top of libqs: schedule, angle conventions, a simulator object and
+a torch.autograd.Function for the adjoint gradient.
+
+arXiv:2604.26423, Sec. II-B: p layers of the cost unitary exp(-i gamma_k H_C)
+(eq. 2) and the mixer exp(+i beta_k H_B) (eq. 3) on |+>^n, with the linear
+ramp of eq. (4).  libqs works in gate angles -- RZZ(theta_zz w_ij) on every
+pair and RX(theta_x) on every qubit -- so this module only maps angles; all
+state arithmetic runs in the HIP library.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import qs as _qs
+
+PRECISIONS = {"c64": _qs.QS_C64, "c128": _qs.QS_C128}
+
+
+# ---------------------------------------------------------------- schedule
+def linear_ramp(p: int, delta_gamma: float, delta_beta: float, form: str = "midpoint"):
+    """Per-layer (gamma_k, beta_k).
+
+    form="paper": eq. (4), gamma_i = (i+1)/p D_gamma, beta_i = (1 - i/p) D_beta, i = 0..p-1.
+    form="midpoint": gamma_k = (k - 1/2)/p D_gamma, beta_k = (1 - (k - 1/2)/p) D_beta, k = 1..p.
+    """
+    if form == "paper":
+        frac_g = [(i + 1) / p for i in range(p)]
+        frac_b = [1 - i / p for i in range(p)]
+    elif form == "midpoint":
+        frac_g = [(k - 0.5) / p for k in range(1, p + 1)]
+        frac_b = [1 - (k - 0.5) / p for k in range(1, p + 1)]
+    else:
+        raise ValueError(form)
+    return (np.array([f * delta_gamma for f in frac_g]), np.array([f * delta_beta for f in frac_b]))
+
+
+def ramp_weights(p: int, form: str = "midpoint"):
+    """d gamma_k / d D_gamma and d beta_k / d D_beta of linear_ramp."""
+    g, b = linear_ramp(p, 1.0, 1.0, form)
+    return g, b
+
+
+# Gate-angle conventions.  "paper": exp(-i gamma H_C) = prod RZZ(2 gamma w_ij),
+# exp(+i beta sum X) = prod RX(-2 beta).  "literal": RZZ(gamma w_ij), RX(2 beta).
+_CONV = {"paper": (2.0, -2.0), "literal": (1.0, 2.0)}
+
+
+def to_gate_angles(gammas, betas, convention: str = "paper"):
+    a, b = _CONV[convention]
+    return a * np.asarray(gammas, dtype=np.float64), b * np.asarray(betas, dtype=np.float64)
+
+
+def gate_grad_to_schedule(d_theta_zz, d_theta_x, convention: str = "paper"):
+    """Chain rule: (dE/dgamma_k, dE/dbeta_k) from (dE/dtheta_zz, dE/dtheta_x)."""
+    a, b = _CONV[convention]
+    return a * np.asarray(d_theta_zz), b * np.asarray(d_theta_x)
+
+
+def n_from_edges(m: int) -> int:
+    n = int(round((1 + math.sqrt(1 + 8 * m)) / 2))
+    if n * (n - 1) // 2 != m:
+        raise ValueError(f"{m} weights is not n(n-1)/2 for any n")
+    return n
+
+
+# ---------------------------------------------------------------- simulator
+class Simulator:
+    """One LR-QAOA instance on one GPU: cost diagonal, state, readouts.
+
+    Device memory (state, diagonal, optional adjoint vector) is held in torch
+    tensors; the HIP stream is torch's current stream at construction.
+    """
+
+    def __init__(self, w_tenths, precision: str = "c64", device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
+        self.n = n_from_edges(len(self.w))
+        self.precision = precision
+        self.prec = PRECISIONS[precision]
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cdt = torch.complex64 if self.prec == _qs.QS_C64 else torch.complex128
+        self.psi = torch.empty(1 << self.n, dtype=cdt, device=self.device)
+        self.diag = torch.empty(1 << self.n, dtype=torch.int32, device=self.device)
+        self.lam: Optional[object] = None
+        self.handle = _qs.qs_alloc(self.n, self.prec, self.psi, self.psi.numel() * self.psi.element_size(),
+                                   self.stream)
+        self.w_total, self.cmax = _qs.qs_cost_diagonal(self.n, self.w, self.diag, self.stream)
+
+    # ---- circuit
+    def forward(self, theta_zz, theta_x, readout: bool = True):
+        return _qs.qs_forward(self.handle, self.diag, self.w_total, theta_zz, theta_x, readout)
+
+    def forward_schedule(self, gammas, betas, convention: str = "paper", readout: bool = True):
+        tzz, tx = to_gate_angles(gammas, betas, convention)
+        return self.forward(tzz, tx, readout)
+
+    def init_plus(self):
+        _qs.qs_init_plus(self.handle)
+
+    def apply_cost_layer(self, theta_zz: float):
+        _qs.qs_apply_cost_layer(self.handle, self.diag, self.w_total, theta_zz)
+
+    def apply_mixer(self, theta_x: float):
+        _qs.qs_apply_mixer(self.handle, theta_x)
+
+    # ---- readouts
+    def expect(self):
+        return _qs.qs_expect(self.handle, self.diag)
+
+    def ratio(self, exp_c: float) -> float:
+        """r = <C> / C(x*) (eq. 5 with exact probabilities)."""
+        return exp_c / (self.cmax / 10.0)
+
+    def sample(self, shots: int, seed: int, on_device: bool = False):
+        if on_device:
+            out = self.torch.empty(shots, dtype=self.torch.int64, device=self.device)
+            return _qs.qs_sample(self.handle, seed, shots, out)
+        return _qs.qs_sample(self.handle, seed, shots)
+
+    def shots_ratio(self, shots) -> float:
+        """r of eq. (5) from sampled bitstrings."""
+        idx = self.torch.as_tensor(np.asarray(shots, dtype=np.int64), device=self.device)
+        cuts = self.diag[idx].double().mean().item() / 10.0
+        return cuts / (self.cmax / 10.0)
+
+    def adjoint(self, theta_zz, theta_x):
+        if self.lam is None:
+            self.lam = self.torch.empty_like(self.psi)
+        return _qs.qs_adjoint_grad(self.handle, self.diag, self.w_total, theta_zz, theta_x, self.lam,
+                                   self.lam.numel() * self.lam.element_size())
+
+    def release_adjoint(self):
+        self.lam = None
+
+    def state(self):
+        return self.psi
+
+    # ---- profiling
+    def profile(self, enable: bool = True):
+        _qs.qs_profile(self.handle, enable)
+
+    def profile_read(self, kind: int):
+        return _qs.qs_profile_read(self.handle, kind)
+
+    def close(self):
+        if self.handle is not None:
+            _qs.qs_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd():
+    import torch
+
+    class ExpectC(torch.autograd.Function):
+        """<C>(gammas, betas) with the adjoint gradient of libqs.
+
+        forward(gammas, betas, sim, convention) runs the circuit and the
+        reverse sweep once; backward scales the stored gradient.
+        """
+
+        @staticmethod
+        def forward(ctx, gammas, betas, sim, convention="paper"):
+            g = gammas.detach().cpu().double().numpy()
+            b = betas.detach().cpu().double().numpy()
+            tzz, tx = to_gate_angles(g, b, convention)
+            e, gzz, gx = sim.adjoint(tzz, tx)
+            dg, db = gate_grad_to_schedule(gzz, gx, convention)
+            ctx.save_for_backward(torch.as_tensor(dg, dtype=gammas.dtype),
+                                  torch.as_tensor(db, dtype=betas.dtype))
+            return torch.tensor(e, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            dg, db = ctx.saved_tensors
+            return grad_out.to(dg.dtype) * dg, grad_out.to(db.dtype) * db, None, None
+
+    return ExpectC
+
+
+_ExpectC = None
+
+
+def expect_c(gammas, betas, sim: Simulator, convention: str = "paper"):
+    """Differentiable <C> as a function of per-layer (gamma_k, beta_k) CPU tensors."""
+    global _ExpectC
+    if _ExpectC is None:
+        _ExpectC = _autograd()
+    return _ExpectC.apply(gammas, betas, sim, convention)

@@ -1,0 +1,225 @@
+"""Thin Python binding of libqs (include/qs.h): argument marshalling only.
+
+Every function keeps the C name and order of arguments.  Device buffers may be
+passed as torch tensors (their data_ptr is used) or as integer addresses;
+streams as torch streams, raw hipStream_t integers, or None for the current
+torch stream.  A non-OK status raises QSError carrying the status and the
+library's message.  The library must have been built (``python -m
+paper_2604_26423_amd.build``); if it is missing every call fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqs.so")
+
+QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_HIP, QS_ERR_RANGE, QS_ERR_STATE = range(6)
+QS_C64, QS_C128 = 0, 1
+QS_MAX_QUBITS_C64, QS_MAX_QUBITS_C128 = 34, 33
+(QS_KIND_PASS, QS_KIND_PASS_PHASE, QS_KIND_ADJOINT, QS_KIND_EXPECT, QS_KIND_SAMPLE,
+ QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_COUNT) = range(9)
+KIND_NAMES = ["pass", "pass_phase", "adjoint", "expect", "sample", "elementwise", "reduce", "small"]
+
+# every symbol the public headers declare
+EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
+           "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_apply_cost_layer", "qs_apply_mixer",
+           "qs_forward", "qs_expect", "qs_sample", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
+           "qs_plan_check"]
+
+
+class QSError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libqs status {status}: {message}")
+        self.status = status
+
+
+_lib = None
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+_c_i32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqs.so from the package directory (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libqs.so not found at {LIB_PATH}: build it with "
+                           "`python -m paper_2604_26423_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz, dbl, u64 = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t,
+                                  ctypes.c_double, ctypes.c_uint64)
+    sig = {
+        "qs_last_error": ([], ctypes.c_char_p),
+        "qs_version": ([], ctypes.c_char_p),
+        "qs_state_bytes": ([i32, i32], sz),
+        "qs_alloc": ([i32, i32, vp, sz, vp, ctypes.POINTER(vp)], i32),
+        "qs_free": ([vp], i32),
+        "qs_state_ptr": ([vp, ctypes.POINTER(vp)], i32),
+        "qs_set_stream": ([vp, vp], i32),
+        "qs_init_plus": ([vp], i32),
+        "qs_cost_diagonal": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
+        "qs_apply_cost_layer": ([vp, vp, i64, dbl], i32),
+        "qs_apply_mixer": ([vp, dbl], i32),
+        "qs_forward": ([vp, vp, i64, i32, vp, vp, _c_dbl_p, _c_dbl_p], i32),
+        "qs_expect": ([vp, vp, _c_dbl_p, _c_dbl_p], i32),
+        "qs_sample": ([vp, u64, i64, vp, i32], i32),
+        "qs_adjoint_grad": ([vp, vp, i64, i32, vp, vp, vp, sz, _c_dbl_p, vp, vp], i32),
+        "qs_profile": ([vp, i32], i32),
+        "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
+        "qs_plan_check": ([i32, i32, i32, ctypes.c_char_p, sz], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != QS_OK:
+        raise QSError(status, lib().qs_last_error().decode(errors="replace"))
+
+
+def _ptr(x) -> Optional[int]:
+    """Device address of a torch tensor, an integer address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def _f64(a: Sequence[float]) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- wrappers
+def qs_last_error() -> str:
+    return lib().qs_last_error().decode(errors="replace")
+
+
+def qs_version() -> str:
+    return lib().qs_version().decode()
+
+
+def qs_state_bytes(n: int, prec: int) -> int:
+    return int(lib().qs_state_bytes(n, prec))
+
+
+def qs_alloc(n: int, prec: int, dev_buf=None, buf_bytes: int = 0, stream=None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(lib().qs_alloc(n, prec, _ptr(dev_buf), buf_bytes, _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def qs_free(s) -> None:
+    _check(lib().qs_free(s))
+
+
+def qs_state_ptr(s) -> int:
+    p = ctypes.c_void_p()
+    _check(lib().qs_state_ptr(s, ctypes.byref(p)))
+    return int(p.value or 0)
+
+
+def qs_set_stream(s, stream=None) -> None:
+    _check(lib().qs_set_stream(s, _stream(stream)))
+
+
+def qs_init_plus(s) -> None:
+    _check(lib().qs_init_plus(s))
+
+
+def qs_cost_diagonal(n: int, w_tenths, diag_dev, stream=None) -> tuple:
+    """Returns (W_t, C_max in tenths)."""
+    w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
+    W, cm = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().qs_cost_diagonal(n, w.ctypes.data if w.size else None, _ptr(diag_dev), ctypes.byref(W),
+                                  ctypes.byref(cm), _stream(stream)))
+    return int(W.value), int(cm.value)
+
+
+def qs_apply_cost_layer(s, diag_dev, w_total_tenths: int, theta_zz: float) -> None:
+    _check(lib().qs_apply_cost_layer(s, _ptr(diag_dev), int(w_total_tenths), float(theta_zz)))
+
+
+def qs_apply_mixer(s, theta_x: float) -> None:
+    _check(lib().qs_apply_mixer(s, float(theta_x)))
+
+
+def qs_forward(s, diag_dev, w_total_tenths: int, theta_zz, theta_x, readout: bool = True):
+    """Returns (exp_c, norm) when readout, else None."""
+    tzz, tx = _f64(theta_zz), _f64(theta_x)
+    if tzz.shape != tx.shape:
+        raise ValueError("theta_zz and theta_x must have the same length")
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_forward(s, _ptr(diag_dev), int(w_total_tenths), len(tzz),
+                            tzz.ctypes.data if len(tzz) else None, tx.ctypes.data if len(tx) else None,
+                            ctypes.byref(e) if readout else None, ctypes.byref(nrm) if readout else None))
+    return (e.value, nrm.value) if readout else None
+
+
+def qs_expect(s, diag_dev) -> tuple:
+    e, nrm = ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_expect(s, _ptr(diag_dev), ctypes.byref(e), ctypes.byref(nrm)))
+    return e.value, nrm.value
+
+
+def qs_sample(s, seed: int, shots: int, out=None) -> np.ndarray:
+    """Shots to a new host array, or into a device tensor `out` (returned)."""
+    if out is not None:
+        _check(lib().qs_sample(s, int(seed), int(shots), _ptr(out), 1))
+        return out
+    host = np.empty(int(shots), dtype=np.uint64)
+    _check(lib().qs_sample(s, int(seed), int(shots), host.ctypes.data if shots > 0 else None, 0))
+    return host
+
+
+def qs_adjoint_grad(s, diag_dev, w_total_tenths: int, theta_zz, theta_x, lambda_buf=None,
+                    lambda_bytes: int = 0) -> tuple:
+    """Returns (E, dE/dtheta_zz[p], dE/dtheta_x[p])."""
+    tzz, tx = _f64(theta_zz), _f64(theta_x)
+    if tzz.shape != tx.shape:
+        raise ValueError("theta_zz and theta_x must have the same length")
+    p = len(tzz)
+    gzz, gx, e = np.empty(p), np.empty(p), ctypes.c_double()
+    _check(lib().qs_adjoint_grad(s, _ptr(diag_dev), int(w_total_tenths), p,
+                                 tzz.ctypes.data if p else None, tx.ctypes.data if p else None,
+                                 _ptr(lambda_buf), int(lambda_bytes), ctypes.byref(e),
+                                 gzz.ctypes.data if p else None, gx.ctypes.data if p else None))
+    return e.value, gzz, gx
+
+
+def qs_profile(s, enable: bool) -> None:
+    _check(lib().qs_profile(s, 1 if enable else 0))
+
+
+def qs_profile_read(s, kind: int) -> tuple:
+    """(launches, total_ms, algorithmic bytes) of one kernel kind."""
+    n, ms, by = ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_profile_read(s, kind, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)))
+    return int(n.value), ms.value, by.value
+
+
+def qs_plan_check(n: int, prec: int, p: int) -> tuple:
+    """Host-only check of the pass plan: (code, message); code 0 = valid."""
+    buf = ctypes.create_string_buffer(512)
+    rc = lib().qs_plan_check(n, prec, p, buf, 512)
+    return int(rc), buf.value.decode()

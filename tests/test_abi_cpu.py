@@ -1,0 +1,127 @@
+"""Host-side tests of libqs: exports, argument validation, the pass plan.
+
+No kernel runs here.  Handles are created over fake (never dereferenced)
+device addresses so that every error path that fails before GPU work can be
+exercised on a machine without a GPU.
+"""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2604_26423_amd import qs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 1 << 40  # 256-byte aligned address that is never touched
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(qs_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    L = qs.lib()
+    names = declared_symbols()
+    assert "qs_adjoint_grad" in names and "qs_plan_check" in names
+    for name in sorted(names):
+        assert hasattr(L, name), name
+    assert set(qs.EXPORTS) == names
+
+
+def test_state_bytes():
+    assert qs.qs_state_bytes(33, qs.QS_C64) == 64 << 30        # Sec. II-E: 2^(N+3) bytes
+    assert qs.qs_state_bytes(34, qs.QS_C64) == 128 << 30
+    assert qs.qs_state_bytes(33, qs.QS_C128) == 128 << 30
+    assert qs.qs_state_bytes(34, qs.QS_C128) == 0
+    assert qs.qs_state_bytes(0, qs.QS_C64) == 0
+    assert qs.qs_state_bytes(5, 7) == 0
+
+
+def expect_status(status, fn, *args, **kw):
+    with pytest.raises(qs.QSError) as ei:
+        fn(*args, **kw)
+    assert ei.value.status == status, str(ei.value)
+    return str(ei.value)
+
+
+def test_alloc_validation():
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 0, qs.QS_C64, FAKE, 1 << 20, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 35, qs.QS_C64, FAKE, 1 << 40, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 34, qs.QS_C128, FAKE, 1 << 40, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 10, 2, FAKE, 1 << 20, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 10, qs.QS_C64, FAKE, 8 * 1023, 0)   # too small
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 10, qs.QS_C64, FAKE + 8, 1 << 20, 0)  # misaligned
+    assert qs.lib().qs_alloc(10, 0, FAKE, 1 << 20, 0, None) == qs.QS_ERR_ARG
+
+
+@pytest.fixture
+def fake_state():
+    h = qs.qs_alloc(16, qs.QS_C64, FAKE, 8 << 16, 0)
+    yield h
+    # qs_free synchronises the stream; without a device that call just fails quietly
+    qs.lib().qs_free(h)
+
+
+def test_entry_point_validation(fake_state):
+    s = fake_state
+    diag = FAKE
+    expect_status(qs.QS_ERR_RANGE, qs.qs_apply_cost_layer, s, diag, 1 << 31, 0.3)
+    expect_status(qs.QS_ERR_ARG, qs.qs_apply_cost_layer, s, None, 100, 0.3)
+    expect_status(qs.QS_ERR_ARG, qs.qs_apply_cost_layer, s, diag + 4, 100, 0.3)     # misaligned
+    expect_status(qs.QS_ERR_ARG, qs.qs_apply_cost_layer, s, diag, 100, float("nan"))
+    expect_status(qs.QS_ERR_ARG, qs.qs_apply_mixer, s, float("inf"))
+    expect_status(qs.QS_ERR_ARG, qs.qs_forward, s, diag, 100, [0.1, float("nan")], [0.1, 0.2])
+    expect_status(qs.QS_ERR_ARG, qs.qs_forward, s, None, 100, [0.1], [0.1])
+    assert qs.lib().qs_forward(s, diag, 100, -1, None, None, None, None) == qs.QS_ERR_ARG
+    expect_status(qs.QS_ERR_ARG, qs.qs_expect, s, None)
+    assert qs.lib().qs_sample(s, 1, -5, None, 0) == qs.QS_ERR_ARG
+    assert qs.lib().qs_sample(s, 1, 10, None, 0) == qs.QS_ERR_ARG
+    expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad, s, diag, 100, [], [])           # p = 0
+    expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad, s, diag, 100, [0.1], [0.2], FAKE, 8 << 16)  # aliases psi
+    expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad, s, diag, 100, [0.1], [0.2], FAKE + (1 << 30), 16)
+    expect_status(qs.QS_ERR_ARG, qs.qs_profile_read, s, 99)
+    assert "null state" in expect_status(qs.QS_ERR_ARG, qs.qs_init_plus, None)
+
+
+def test_cost_diagonal_validation():
+    w = np.ones(45, dtype=np.int32)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 0, w, FAKE, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 35, w, FAKE, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, w, None, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, w, FAKE + 4, 0)
+    bad = w.copy()
+    bad[7] = -1
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, bad, FAKE, 0)
+    bad[7] = 1 << 20
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, bad, FAKE, 0)
+
+
+def test_last_error_is_thread_local():
+    import threading
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 0, qs.QS_C64, FAKE, 1 << 20, 0)
+    seen = {}
+
+    def other():
+        seen["msg"] = qs.qs_last_error()
+    t = threading.Thread(target=other)
+    t.start()
+    t.join()
+    assert seen["msg"] == ""
+    assert "outside" in qs.qs_last_error()
+
+
+@pytest.mark.parametrize("prec", [qs.QS_C64, qs.QS_C128])
+def test_pass_plan(prec):
+    """The exact planner the kernels use: coverage, bijections, layer order."""
+    for n in range(1, (34 if prec == qs.QS_C64 else 33) + 1):
+        for p in ((1, 2, 3, 4, 7) if n <= 24 else (1, 3, 10)):
+            rc, msg = qs.qs_plan_check(n, prec, p)
+            assert rc == 0, (n, p, msg)
+    assert qs.qs_plan_check(0, prec, 1)[0] == 2

@@ -137,7 +137,19 @@ struct Circuit {
     const double *tzz, *tx;
 };
 
-PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc)
+// RX(theta) of one stage over m qubits: tangent form when |cos(theta/2)| >= 1/2.
+RxStage rx_stage(double theta, int m, double *factor)
+{
+    RxStage st{};
+    st.c = cos(0.5 * theta);
+    st.s = sin(0.5 * theta);
+    st.tan = fabs(st.c) >= 0.5 ? 1 : 0;
+    st.u = st.tan ? st.s / st.c : 0.0;
+    *factor = st.tan ? pow(st.c, m) : 1.0;
+    return st;
+}
+
+PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb)
 {
     const int T = tile_bits(s->prec);
     PassProg pp{};
@@ -145,39 +157,55 @@ PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit 
     pp.lam = nullptr;
     pp.diag = cc.diag;
     pp.partials = (double *)s->partials.p;
+    pp.ntiles = (int64_t)1 << (s->n - T);
     pp.n = s->n;
     pp.c = g.c;
     pp.q0 = g.q0;
     pp.targets = g.targets;
-    const int64_t grid = (int64_t)1 << (s->n - T);
-    pp.xcd_remap = (grid % 8 == 0) ? 1 : 0;
+    pp.ntargets = __builtin_popcount(g.targets);
+    pp.width = T - g.c;
     pp.init = k.init;
     pp.has_pre = k.pre >= 0;
     pp.has_phase = k.phase >= 0;
     pp.has_post = k.post >= 0;
     pp.readout = k.readout;
-    pp.load_win = 8;
+    pp.load_win = tb;
+    pp.fpre = pp.fpost = 1.0;
     if (pp.has_pre) {
-        pp.A = plan_windows(8, g.targets, T);
-        pp.B = plan_windows(pp.A.s[pp.A.cnt - 1], g.targets, T);
-        pp.pre_c = cos(0.5 * cc.tx[k.pre]);
-        pp.pre_s = sin(0.5 * cc.tx[k.pre]);
+        pp.A = plan_windows(tb, g.targets, T, tb);
+        pp.B = plan_windows(pp.A.s[pp.A.cnt - 1], g.targets, T, tb);
+        pp.pre = rx_stage(cc.tx[k.pre], pp.ntargets, &pp.fpre);
     } else {
-        pp.B = plan_windows(8, g.targets, T);
+        pp.B = plan_windows(tb, g.targets, T, tb);
     }
-    if (pp.has_post) {
-        pp.post_c = cos(0.5 * cc.tx[k.post]);
-        pp.post_s = sin(0.5 * cc.tx[k.post]);
-    }
+    if (pp.has_post) pp.post = rx_stage(cc.tx[k.post], pp.ntargets, &pp.fpost);
+    pp.factor = pp.fpre * pp.fpost;
+    pp.phase_win = pp.has_pre ? pp.A.s[pp.A.cnt - 1] : pp.load_win;
+    pp.final_win = pp.B.s[pp.B.cnt - 1];
     if (pp.has_phase) pp.theta_zz = cc.tzz[k.phase];
     pp.W = cc.W;
-    pp.phase_table = cc.W < kPhaseTableMaxW ? 1 : 0;
+    pp.phase_levels = phase_table_levels(cc.W);
     pp.amp0 = sqrt(ldexp(1.0, -s->n));
     return pp;
 }
 
-// Final layout of a forward kernel (where it stores; where its reverse loads).
-int final_win(const PassProg &pp) { return pp.B.s[pp.B.cnt - 1]; }
+// Launch one tile kernel over a persistent grid; returns the grid (the number
+// of per-workgroup partial sums it writes).
+qs_status launch_tiles(qs_state s, PassProg &pp, int adjoint, int turnaround, int kind, double bytes,
+                       int64_t *grid_out, const char *where)
+{
+    // adjoint: 0 = forward pass, 1 = turnaround, 2 = reverse pass
+    const int64_t grid = pass_grid(s->prec, adjoint, pp.ntiles);
+    pp.xcd_remap = (grid % 8 == 0) ? 1 : 0;
+    Launch L(s, kind, bytes);
+    HIPCHK(adjoint ? launch_adjoint_pass(s->prec, pp, turnaround, grid, s->stream)
+                   : launch_pass(s->prec, pp, grid, s->stream),
+           where);
+    L.done();
+    if (grid_out) *grid_out = grid;
+    return QS_OK;
+}
+
 
 double pass_bytes(qs_state s, const PassProg &pp)
 {
@@ -308,13 +336,13 @@ qs_status run_forward(qs_state s, const Circuit &cc, bool readout, const char *w
     const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
     std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     if (readout) ks.back().readout = 1;
-    const int64_t grid = (int64_t)1 << (s->n - T);
-    HIPCHK(ensure_partials(s, grid), where);
+    HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
+    int64_t grid = 0;
     for (const KSpec &k : ks) {
-        PassProg pp = make_prog(s, geo[k.pass], k, cc);
-        Launch L(s, pp.has_phase ? QS_KIND_PASS_PHASE : QS_KIND_PASS, pass_bytes(s, pp));
-        HIPCHK(launch_pass(s->prec, pp, grid, s->stream), where);
-        L.done();
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kFwdThreadBits);
+        if (qs_status st = launch_tiles(s, pp, 0, 0, pp.has_phase ? QS_KIND_PASS_PHASE : QS_KIND_PASS,
+                                        pass_bytes(s, pp), &grid, where))
+            return st;
     }
     if (readout) {
         const int map[kSlots] = {0, 1, -1, -1};
@@ -366,43 +394,39 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
 
     const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
     const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
-    const int64_t grid = (int64_t)1 << (s->n - T);
-    HIPCHK(ensure_partials(s, grid), where);
+    const int64_t ntiles = (int64_t)1 << (s->n - T);
+    HIPCHK(ensure_partials(s, std::max(pass_grid(s->prec, 0, ntiles), pass_grid(s->prec, 1, ntiles))), where);
     const double dim = ldexp(1.0, s->n), ab = (double)amp_bytes(s->prec);
+    int64_t grid = 0;
 
     // forward, all but the last pass
     for (size_t i = 0; i + 1 < ks.size(); ++i) {
-        PassProg pp = make_prog(s, geo[ks[i].pass], ks[i], cc);
-        Launch L(s, pp.has_phase ? QS_KIND_PASS_PHASE : QS_KIND_PASS, pass_bytes(s, pp));
-        HIPCHK(launch_pass(s->prec, pp, grid, s->stream), where);
-        L.done();
+        PassProg pp = make_prog(s, geo[ks[i].pass], ks[i], cc, kFwdThreadBits);
+        if (qs_status st = launch_tiles(s, pp, 0, 0, pp.has_phase ? QS_KIND_PASS_PHASE : QS_KIND_PASS,
+                                        pass_bytes(s, pp), &grid, where))
+            return st;
     }
     // turnaround: the last pass forward, lambda = C psi, the pass undone
     {
         const KSpec &k = ks.back();
-        PassProg pp = make_prog(s, geo[k.pass], k, cc);
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
         pp.lam = lam;
-        Launch L(s, QS_KIND_ADJOINT, dim * (ab + 4 + ab));
-        HIPCHK(launch_adjoint_pass(s->prec, pp, 1, grid, s->stream), where);
-        L.done();
+        if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_ADJOINT, dim * (ab + 4 + ab), &grid, where))
+            return st;
         const int map[kSlots] = {2 + cc.p + k.post, 0, 1, -1};
-        qs_status st = run_reduce(s, grid, map, 1, where);
-        if (st != QS_OK) return st;
+        if (qs_status st = run_reduce(s, grid, map, 1, where)) return st;
     }
     // reverse passes
     for (int i = (int)ks.size() - 2; i >= 0; --i) {
         const KSpec &k = ks[i];
-        PassProg pp = make_prog(s, geo[k.pass], k, cc);
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
         pp.lam = lam;
-        pp.load_win = final_win(pp);
-        double by = dim * ab * (pp.init ? 2.0 : 4.0) + (pp.has_phase ? dim * 4.0 : 0.0);
-        Launch L(s, QS_KIND_ADJOINT, by);
-        HIPCHK(launch_adjoint_pass(s->prec, pp, 0, grid, s->stream), where);
-        L.done();
+        pp.load_win = pp.final_win;
+        const double by = dim * ab * (pp.init ? 2.0 : 4.0) + (pp.has_phase ? dim * 4.0 : 0.0);
+        if (qs_status st = launch_tiles(s, pp, 2, 0, QS_KIND_ADJOINT, by, &grid, where)) return st;
         const int map[kSlots] = {k.post >= 0 ? 2 + cc.p + k.post : -1, k.phase >= 0 ? 2 + k.phase : -1,
                                  k.pre >= 0 ? 2 + cc.p + k.pre : -1, -1};
-        qs_status st = run_reduce(s, grid, map, 1, where);
-        if (st != QS_OK) return st;
+        if (qs_status st = run_reduce(s, grid, map, 1, where)) return st;
     }
     return QS_OK;
 }
@@ -580,16 +604,13 @@ qs_status qs_apply_mixer(qs_state s, double theta_x)
         return QS_OK;
     }
     const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
-    const int64_t grid = (int64_t)1 << (s->n - T);
-    HIPCHK(ensure_partials(s, grid), where);
+    HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
     const double tx[1] = {theta_x}, tzz[1] = {0.0};
     Circuit cc{nullptr, 0, 1, tzz, tx};
     for (size_t i = 0; i < geo.size(); ++i) {
         KSpec k{(int)i, 0, -1, -1, 0, 0};
-        PassProg pp = make_prog(s, geo[i], k, cc);
-        Launch L(s, QS_KIND_PASS, pass_bytes(s, pp));
-        HIPCHK(launch_pass(s->prec, pp, grid, s->stream), where);
-        L.done();
+        PassProg pp = make_prog(s, geo[i], k, cc, kFwdThreadBits);
+        if (qs_status st = launch_tiles(s, pp, 0, 0, QS_KIND_PASS, pass_bytes(s, pp), nullptr, where)) return st;
     }
     return QS_OK;
 }

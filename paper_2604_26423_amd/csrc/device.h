@@ -18,11 +18,12 @@ __device__ __forceinline__ V cmul(V a, V b)
     return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// FP64 phase argument reduced to (-pi, pi].
+// FP64 phase argument reduced to about [-pi, pi].
 __device__ __forceinline__ double reduce_2pi(double a)
 {
     const double two_pi = 6.283185307179586476925286766559;
-    return a - two_pi * rint(a / two_pi);
+    const double inv_two_pi = 0.15915494309189533576888376337251;
+    return a - two_pi * rint(a * inv_two_pi);
 }
 
 // exp(i a) for an FP64 argument, rounded to the state precision.
@@ -63,45 +64,93 @@ __device__ __forceinline__ void rx_reg_bit(V (&v)[NR], R c, R s)
 template <typename V, int NR, typename R>
 __device__ __forceinline__ void rx_reg_mask(V (&v)[NR], uint32_t mask, R c, R s)
 {
-    if (mask & 1u) rx_reg_bit<0>(v, c, s);
-    if (mask & 2u) rx_reg_bit<1>(v, c, s);
-    if (mask & 4u) rx_reg_bit<2>(v, c, s);
-    if (mask & 8u) rx_reg_bit<3>(v, c, s);
+    if constexpr (NR > 1) { if (mask & 1u) rx_reg_bit<0>(v, c, s); }
+    if constexpr (NR > 2) { if (mask & 2u) rx_reg_bit<1>(v, c, s); }
+    if constexpr (NR > 4) { if (mask & 4u) rx_reg_bit<2>(v, c, s); }
+    if constexpr (NR > 8) { if (mask & 8u) rx_reg_bit<3>(v, c, s); }
     if constexpr (NR >= 32) { if (mask & 16u) rx_reg_bit<4>(v, c, s); }
     if constexpr (NR >= 64) { if (mask & 32u) rx_reg_bit<5>(v, c, s); }
 }
 
+// Tangent form: (a0, a1) <- (a0 - i u a1, a1 - i u a0) = RX(theta)/cos(theta/2) on
+// the pair when u = tan(theta/2).
+template <typename V, typename R>
+__device__ __forceinline__ void rxt_pair(V &a0, V &a1, R u)
+{
+    const V b0{a0.x + u * a1.y, a0.y - u * a1.x};
+    const V b1{a1.x + u * a0.y, a1.y - u * a0.x};
+    a0 = b0;
+    a1 = b1;
+}
+
+template <int K, typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_bit(V (&v)[NR], R u)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) rxt_pair(v[r], v[r | (1 << K)], u);
+}
+
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_mask(V (&v)[NR], uint32_t mask, R u)
+{
+    if constexpr (NR > 1) { if (mask & 1u) rxt_reg_bit<0>(v, u); }
+    if constexpr (NR > 2) { if (mask & 2u) rxt_reg_bit<1>(v, u); }
+    if constexpr (NR > 4) { if (mask & 4u) rxt_reg_bit<2>(v, u); }
+    if constexpr (NR > 8) { if (mask & 8u) rxt_reg_bit<3>(v, u); }
+    if constexpr (NR >= 32) { if (mask & 16u) rxt_reg_bit<4>(v, u); }
+    if constexpr (NR >= 64) { if (mask & 32u) rxt_reg_bit<5>(v, u); }
+}
+
+// RX of a stage on the register bits in mask; sign = -1 applies RX(-theta).
+template <typename V, int NR>
+__device__ __forceinline__ void stage_rx(V (&v)[NR], uint32_t mask, const RxStage &st, int sign)
+{
+    using R = typename Real<V>::T;
+    if (st.tan) rxt_reg_mask(v, mask, (R)(sign * st.u));
+    else rx_reg_mask(v, mask, (R)st.c, (R)(sign * st.s));
+}
+
 // Im <lam| X_q |psi> restricted to the pairs held in registers, for register bit K:
 // sum over pairs of Im(conj(l0) p1) + Im(conj(l1) p0), accumulated in FP64.
+// The pair terms of one register bit (NR/2 pairs held by the thread) are
+// summed in the state precision; the result joins an FP64 accumulator.
 template <int K, typename V, int NR>
 __device__ __forceinline__ double imx_reg_bit(const V (&l)[NR], const V (&p)[NR])
 {
-    double acc = 0.0;
+    using R = typename Real<V>::T;
+    R acc = 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         if (!(r & (1 << K))) {
             const V l0 = l[r], l1 = l[r | (1 << K)], p0 = p[r], p1 = p[r | (1 << K)];
-            acc += (double)l0.x * (double)p1.y - (double)l0.y * (double)p1.x;
-            acc += (double)l1.x * (double)p0.y - (double)l1.y * (double)p0.x;
+            acc += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
         }
-    return acc;
+    return (double)acc;
 }
 
 template <typename V, int NR>
 __device__ __forceinline__ double imx_reg_mask(const V (&l)[NR], const V (&p)[NR], uint32_t mask)
 {
     double acc = 0.0;
-    if (mask & 1u) acc += imx_reg_bit<0>(l, p);
-    if (mask & 2u) acc += imx_reg_bit<1>(l, p);
-    if (mask & 4u) acc += imx_reg_bit<2>(l, p);
-    if (mask & 8u) acc += imx_reg_bit<3>(l, p);
+    if constexpr (NR > 1) { if (mask & 1u) acc += imx_reg_bit<0>(l, p); }
+    if constexpr (NR > 2) { if (mask & 2u) acc += imx_reg_bit<1>(l, p); }
+    if constexpr (NR > 4) { if (mask & 4u) acc += imx_reg_bit<2>(l, p); }
+    if constexpr (NR > 8) { if (mask & 8u) acc += imx_reg_bit<3>(l, p); }
     if constexpr (NR >= 32) { if (mask & 16u) acc += imx_reg_bit<4>(l, p); }
     if constexpr (NR >= 64) { if (mask & 32u) acc += imx_reg_bit<5>(l, p); }
     return acc;
 }
 
-// LDS address of tile element e: one pad element every 32 to spread banks.
-__device__ __forceinline__ int lds_index(int e) { return e + (e >> 5); }
+// LDS slot of tile element e: an XOR swizzle of the low RB bits with the next
+// RB bits, which keeps every window layout free of bank conflicts.  It is
+// linear over GF(2), so the slot of (thread part | register part) is the XOR
+// of the two slots: a per-thread constant and a per-register uniform value.
+template <int RB>
+__host__ __device__ __forceinline__ int lds_slot(int e)
+{
+    return e ^ ((e >> RB) & ((1 << RB) - 1));
+}
 
 // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
 // XCD works on a contiguous range of tiles (neighbouring tiles share L2 lines
@@ -113,17 +162,25 @@ __device__ __forceinline__ int64_t xcd_tile(int remap)
     return (b & 7) * (g >> 3) + (b >> 3);
 }
 
+template <typename V>
+__device__ __forceinline__ V scale_v(V a, typename Real<V>::T f)
+{
+    return V{a.x * f, a.y * f};
+}
+
 // Move the NR amplitudes of every thread from layout `from` to layout `to`
 // through LDS.  Leading barrier: earlier LDS reads of this buffer are done.
-template <typename V, int NR>
-__device__ __forceinline__ void exchange(V (&v)[NR], V *lds, int from, int to, int tid, int rb)
+template <int RB, typename V, int NR>
+__device__ __forceinline__ void exchange(V (&v)[NR], V *lds, int from, int to, int tid)
 {
+    const int tf = lds_slot<RB>(win_elem(0, tid, from, RB));
+    const int tt = lds_slot<RB>(win_elem(0, tid, to, RB));
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) lds[lds_index(win_elem(r, tid, from, rb))] = v[r];
+    for (int r = 0; r < NR; ++r) lds[tf ^ lds_slot<RB>(r << from)] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = lds[lds_index(win_elem(r, tid, to, rb))];
+    for (int r = 0; r < NR; ++r) v[r] = lds[tt ^ lds_slot<RB>(r << to)];
 }
 
 // Deterministic workgroup sum of NV doubles (fixed shuffle tree, then waves in

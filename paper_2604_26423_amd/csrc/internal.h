@@ -7,11 +7,15 @@
 
 namespace qs {
 
-constexpr int kThreads = 256;         // threads per workgroup of the tile kernels
+constexpr int kThreads = 256;         // threads per workgroup of the elementwise kernels
+#ifndef QS_FWD_TB
+#define QS_FWD_TB 8
+#endif
+constexpr int kFwdThreadBits = QS_FWD_TB; // forward tile kernels: 256 threads
+constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
 constexpr int kMaxWindows = 4;        // register windows per butterfly stage
-constexpr int kPhaseTableMaxW = 8192; // W_t below this: two-level phase table in LDS
 constexpr int kSmallMaxLayers = 32;   // layers per launch of the single-workgroup kernel
 constexpr int kSlots = 4;             // FP64 partial sums per workgroup
 
@@ -19,7 +23,8 @@ inline int tile_bits(int prec) { return prec == 0 ? kTileBitsC64 : kTileBitsC128
 
 // Butterfly stage: a sequence of register windows.  In window s a thread's
 // register index r holds tile bits [s, s + RB); its thread index fills the
-// remaining tile bits in order.  s = 8 is the "natural" layout.
+// remaining tile bits in order.  With 2^TB threads, s = TB is the "natural"
+// layout (consecutive threads hold consecutive tile elements).
 struct WinSeq {
     int cnt;
     int s[kMaxWindows];
@@ -29,23 +34,39 @@ struct WinSeq {
 // [0, c) are the "carrier" bits, equal to global bits [0, c) (contiguous
 // runs in memory), and tile bits [c, T) are the target qubits
 // [q0, q0 + T - c).  The workgroup index supplies the other global bits.
+// RX(theta) on the targets of one butterfly stage.  With |cos(theta/2)| >= 1/2
+// the stage applies the tangent form (a0 - i u a1, a1 - i u a0), u = tan(theta/2),
+// which is RX(theta) / cos(theta/2): two fused multiply-adds per amplitude; the
+// factor cos(theta/2)^m of the stage's m qubits is applied once per kernel.
+// Otherwise it applies RX directly with c = cos(theta/2), s = sin(theta/2).
+struct RxStage {
+    double c, s, u;
+    int tan;
+};
+
 struct PassProg {
     void *psi;            // state (float2 / double2)
     void *lam;            // adjoint vector (reverse kernels only)
     const int32_t *diag;  // cost diagonal in tenths
     double *partials;     // kSlots doubles per workgroup
+    int64_t ntiles;       // 2^(n - T); workgroups loop over tiles
     int n, c, q0;
     uint32_t targets;     // mask of tile bits that are gate targets: [c, T)
+    int ntargets;         // popcount(targets)
+    int width;            // strided tile bits T - c
     int xcd_remap;        // map consecutive tiles to one XCD
     int init;             // start from |+>^n instead of loading
     int has_pre, has_phase, has_post, readout;
     int load_win;         // layout of the first global access
+    int phase_win;        // layout in which the phase is applied (end of stage A)
+    int final_win;        // layout after stage B (store, readout)
     WinSeq A, B;          // windows of the pre and post butterfly stages
-    double pre_c, pre_s;  // RX(theta_pre): cos, sin of theta/2
-    double post_c, post_s;
+    RxStage pre, post;
+    double fpre, fpost;   // tangent-form factors cos(theta/2)^m of the stages (1 if direct)
+    double factor;        // fpre * fpost
     double theta_zz;      // phase angle of the fused cost layer
     int64_t W;            // W_t
-    int phase_table;      // 1: two-level table, 0: per-element FP64 argument
+    int phase_levels;     // digits of the phase table (see pass.hip)
     double amp0;          // 2^(-n/2)
 };
 
@@ -73,31 +94,29 @@ __host__ __device__ __forceinline__ int64_t tile_base(int64_t w, int c, int q0, 
     return (wl << c) | (wh << (q0 + m));
 }
 
-// Global index of (register r, thread) in window s.  When the window starts at
-// or above the carrier bits (s >= c) its register bits are contiguous global
-// bits and the index is the thread's r = 0 element plus r << sh; otherwise
-// (passes with more than 8 carrier bits) each register bit is mapped apart.
+// Global index of (register r, thread) in window s.  Every window starts at
+// or above the carrier bits (s >= c, guaranteed by the pass plan), so its
+// register bits are contiguous global bits and the index is the thread's
+// r = 0 element plus r << sh.
 struct Addr {
     int64_t tg;
-    int sh, s, c, q0;
-    bool fast;
+    int sh;
+    bool fast;  // s >= c (checked by the host plan checker)
     __host__ __device__ __forceinline__ int64_t fast_idx(int r) const { return tg + ((int64_t)r << sh); }
-    __host__ __device__ __forceinline__ int64_t slow_idx(int r) const
-    {
-        const int e = r << s;
-        return tg + (int64_t)(e & ((1 << c) - 1)) + ((int64_t)(e >> c) << q0);
-    }
 };
 
 __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_t base, int c, int q0)
 {
-    return Addr{tile_gidx(win_elem(0, tid, s, rb), base, c, q0), q0 + s - c, s, c, q0, s >= c};
+    return Addr{tile_gidx(win_elem(0, tid, s, rb), base, c, q0), q0 + s - c, s >= c};
 }
 
 // Host-side launchers (one per kernel family); all return hipError_t.
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
+int phase_table_levels(int64_t W);
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid,
                                hipStream_t st);
+// Grid of a tile kernel (kind 0 = forward, 1 = turnaround, 2 = reverse pass).
+int64_t pass_grid(int prec, int adjoint, int64_t ntiles);
 
 // Single-workgroup kernels for n <= T: a chunk of up to kSmallMaxLayers layers.
 struct SmallProg {

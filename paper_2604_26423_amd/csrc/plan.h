@@ -29,6 +29,12 @@ inline int cmin_for(int prec)
     return 3;
 }
 
+// Passes of one mixer layer.  Pass 0 is the contiguous low tile (qubits
+// 0..T-1).  The remaining n - T qubits are split as evenly as possible over
+// strided passes of at most T - cmin targets.  A strided pass keeps c <= 8
+// carrier bits (so every register window starts at or above them); when it
+// has fewer than T - c targets, its lowest strided tile bits are qubits that
+// an earlier pass already handled and are not targets.
 inline std::vector<PassGeom> plan_passes(int n, int prec)
 {
     const int T = tile_bits(prec);
@@ -38,27 +44,29 @@ inline std::vector<PassGeom> plan_passes(int n, int prec)
     if (rem <= 0) return v;
     const int cap = T - cmin_for(prec);
     const int np = (rem + cap - 1) / cap;
-    int q0 = T;
+    int qa = T;  // first target qubit of the next pass
     for (int i = 0; i < np; ++i) {
         const int m = rem / np + (i < rem % np ? 1 : 0);
-        const int c = T - m;
-        v.push_back(PassGeom{c, q0, ((1u << T) - 1u) & ~((1u << c) - 1u)});
-        q0 += m;
+        const int c = std::min(T - m, 8);
+        const int q0 = qa + m - (T - c);  // strided bits end at the last target
+        v.push_back(PassGeom{c, q0, ((1u << T) - 1u) & ~((1u << (T - m)) - 1u)});
+        qa += m;
     }
     return v;
 }
 
-// Window sequence covering all target bits, starting from window `start`.
-inline WinSeq plan_windows(int start, uint32_t targets, int T)
+// Window sequence covering all target bits, starting from window `start`,
+// for a kernel with 2^tb threads (windows start at or below tb).
+inline WinSeq plan_windows(int start, uint32_t targets, int T, int tb)
 {
-    const int rb = T - 8;
+    const int rb = T - tb;
     WinSeq w{};
     w.cnt = 0;
     w.s[w.cnt++] = start;
     uint32_t done = targets & (((1u << rb) - 1u) << start);
     while (targets & ~done) {
         const int low = __builtin_ctz(targets & ~done);
-        const int s = std::min(low, 8);
+        const int s = std::min(low, tb);
         w.s[w.cnt++] = s;
         done |= targets & (((1u << rb) - 1u) << s);
     }

@@ -13,6 +13,12 @@ using namespace qs;
 
 namespace {
 
+template <int RB>
+int lds_slot_host(int e)
+{
+    return e ^ ((e >> RB) & ((1 << RB) - 1));
+}
+
 struct Report {
     char *msg;
     size_t len;
@@ -32,9 +38,9 @@ struct Report {
 
 uint32_t window_mask(int s, int rb) { return ((1u << rb) - 1u) << s; }
 
-int check_windows(Report &R, const WinSeq &w, uint32_t targets, int T, const char *what)
+int check_windows(Report &R, const WinSeq &w, uint32_t targets, int T, int tb, const char *what)
 {
-    const int rb = T - 8;
+    const int rb = T - tb;
     if (w.cnt < 1 || w.cnt > kMaxWindows) return R.fail("%s: %d windows", what, w.cnt);
     uint32_t cov = 0;
     for (int i = 0; i < w.cnt; ++i) {
@@ -45,22 +51,28 @@ int check_windows(Report &R, const WinSeq &w, uint32_t targets, int T, const cha
     return 0;
 }
 
-int check_layout(Report &R, int s, int T)
+int check_layout(Report &R, int s, int T, int tb)
 {
-    const int rb = T - 8, nr = 1 << rb;
+    const int rb = T - tb, nr = 1 << rb;
     std::vector<char> seen(1u << T, 0);
-    for (int tid = 0; tid < kThreads; ++tid)
+    for (int tid = 0; tid < (1 << tb); ++tid)
         for (int r = 0; r < nr; ++r) {
             const int e = win_elem(r, tid, s, rb);
             if (e < 0 || e >= (1 << T)) return R.fail("window %d: element %d out of the tile", s, e);
             if (seen[e]++) return R.fail("window %d: element %d held twice", s, e);
         }
+    // the XOR swizzle of LDS slots is a bijection of the tile
+    std::vector<char> used(1u << T, 0);
+    for (int e = 0; e < (1 << T); ++e) {
+        const int sl = rb == 5 ? lds_slot_host<5>(e) : rb == 4 ? lds_slot_host<4>(e) : lds_slot_host<3>(e);
+        if (sl < 0 || sl >= (1 << T) || used[sl]++) return R.fail("LDS swizzle (RB %d) is not a bijection", rb);
+    }
     return 0;
 }
 
-int check_tile_maps(Report &R, int n, int T, const PassGeom &g, const WinSeq *seqs, int nseq)
+int check_tile_maps(Report &R, int n, int T, int tb, const PassGeom &g, const WinSeq *seqs, int nseq)
 {
-    const int rb = T - 8, nr = 1 << rb, m = T - g.c;
+    const int rb = T - tb, nr = 1 << rb, m = T - g.c;
     const int64_t grid = (int64_t)1 << (n - T), dim = (int64_t)1 << n;
     // workgroups to visit: all of them for n <= 24, else a sample
     std::vector<int64_t> ws;
@@ -87,12 +99,12 @@ int check_tile_maps(Report &R, int n, int T, const PassGeom &g, const WinSeq *se
         for (int q = 0; q < nseq; ++q)
             for (int i = 0; i < seqs[q].cnt; ++i) {
                 const int s = seqs[q].s[i];
-                for (int tid = 0; tid < kThreads; tid += 37) {
+                for (int tid = 0; tid < (1 << tb); tid += 37) {
                     const Addr a = win_addr(tid, s, rb, base, g.c, g.q0);
+                    if (!a.fast) return R.fail("window %d below the carrier bits (c = %d)", s, g.c);
                     for (int r = 0; r < nr; ++r) {
                         const int64_t want = tile_gidx(win_elem(r, tid, s, rb), base, g.c, g.q0);
-                        if (a.slow_idx(r) != want) return R.fail("window %d: general index map wrong", s);
-                        if (a.fast && a.fast_idx(r) != want) return R.fail("window %d: fast index map wrong", s);
+                        if (a.fast_idx(r) != want) return R.fail("window %d: index map wrong", s);
                     }
                 }
             }
@@ -150,29 +162,34 @@ extern "C" int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len)
     std::vector<int> owner(n, -1);
     for (size_t i = 0; i < geo.size(); ++i) {
         const PassGeom &g = geo[i];
-        const int m = T - g.c;
-        if (g.c < 0 || g.c >= T) return R.fail("pass %zu: carrier bits %d", i, g.c);
-        if (g.targets != (((1u << T) - 1u) & ~((1u << g.c) - 1u))) return R.fail("pass %zu: target mask", i);
-        if (i == 0 && (g.c != 0 || g.q0 != 0)) return R.fail("first pass must be the low tile");
+        const int w = T - g.c;                       // strided tile bits
+        const int m = __builtin_popcount(g.targets); // target qubits
+        if (g.c < 0 || g.c > 8) return R.fail("pass %zu: carrier bits %d", i, g.c);
+        if (m < 1 || g.targets != (((1u << T) - 1u) & ~((1u << (T - m)) - 1u)))
+            return R.fail("pass %zu: targets must be the top tile bits", i);
+        if (m > w) return R.fail("pass %zu: more targets than strided bits", i);
+        if (i == 0 && (g.c != 0 || g.q0 != 0 || m != T)) return R.fail("first pass must be the low tile");
         if (i > 0 && g.q0 < g.c) return R.fail("pass %zu: q0 below the carriers", i);
-        if (g.q0 + m > n) return R.fail("pass %zu: targets beyond n", i);
-        for (int q = g.q0; q < g.q0 + m; ++q) {
+        if (g.q0 + w > n) return R.fail("pass %zu: tile beyond n", i);
+        for (int q = g.q0 + w - m; q < g.q0 + w; ++q) {
             if (owner[q] >= 0) return R.fail("qubit %d in passes %d and %zu", q, owner[q], i);
             owner[q] = (int)i;
         }
     }
     for (int q = 0; q < n; ++q)
         if (owner[q] < 0) return R.fail("qubit %d in no pass", q);
-    for (int s = 0; s + (T - 8) <= T; ++s)
-        if (check_layout(R, s, T)) return 1;
-    for (const PassGeom &g : geo) {
-        WinSeq seq[3];
-        seq[0] = plan_windows(8, g.targets, T);                    // single stage
-        seq[1] = plan_windows(8, g.targets, T);                    // pre stage
-        seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, T);  // post stage after pre
-        if (check_windows(R, seq[0], g.targets, T, "single stage")) return 1;
-        if (check_windows(R, seq[2], g.targets, T, "post stage")) return 1;
-        if (check_tile_maps(R, n, T, g, seq, 3)) return 1;
+    for (int tb : {kFwdThreadBits, kAdjThreadBits}) {
+        for (int s = 0; s <= tb; ++s)
+            if (check_layout(R, s, T, tb)) return 1;
+        for (const PassGeom &g : geo) {
+            WinSeq seq[3];
+            seq[0] = plan_windows(tb, g.targets, T, tb);                         // single stage
+            seq[1] = plan_windows(tb, g.targets, T, tb);                         // pre stage
+            seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, T, tb);   // post stage after pre
+            if (check_windows(R, seq[0], g.targets, T, tb, "single stage")) return 1;
+            if (check_windows(R, seq[2], g.targets, T, tb, "post stage")) return 1;
+            if (check_tile_maps(R, n, T, tb, g, seq, 3)) return 1;
+        }
     }
     if (check_schedule(R, (int)geo.size(), p)) return 1;
     // the XCD renumbering is a bijection whenever it is enabled (grid % 8 == 0)

@@ -92,13 +92,17 @@ def test_forward_amplitudes(n, p, precision):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_forward_random_angles_and_large_weights(precision):
-    """Per-element phase path (W_t >= 8192) and arbitrary angles."""
+@pytest.mark.parametrize("wmax,levels", [(2, 1), (300, 3), (1 << 20, 5)])
+def test_forward_random_angles_and_weight_ranges(precision, wmax, levels):
+    """Phase tables of 1, 3 and 5 levels (W_t < 128, < 2^19, < 2^31) and arbitrary angles."""
     n, p = 16, 3
-    w = np.random.default_rng(5).integers(0, 300, size=n * (n - 1) // 2).astype(np.int32)
+    w = np.random.default_rng(5).integers(0, wmax, size=n * (n - 1) // 2).astype(np.int32)
+    W = int(w.sum())
+    assert (levels == 1 and W < 128) or (levels == 3 and 8192 <= W < 1 << 19) or (levels == 5 and W >= 1 << 25)
     tzz, tx = workloads.random_angles(p, 9, scale=2.5)
+    if levels == 5:
+        tzz = tzz * 1e-4   # keep the phases of order one for such large cuts
     sim = sim_for(w, precision)
-    assert sim.w_total >= 8192
     e, _ = sim.forward(tzz, tx)
     ref = oracle.simulate(n, w, tzz, tx, mode=1)
     tol = 1e-5 if precision == "c64" else 1e-12

@@ -24,10 +24,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2604_26423_amd/csrc/pass.hip", "paper_2604_26423_amd/csrc/device.h",
+                  "paper_2604_26423_amd/csrc/internal.h", "paper_2604_26423_amd/csrc/plan.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or None
+    when the file is absent or the kernel sources changed since it was written."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def copy_calibration(torch, gib: int = 4):
+    """Bandwidth of a plain device copy of known size (the achievable ceiling)."""
+    a = torch.ones(gib << 27, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    ts = []
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    t = min(ts[1:])
+    nbytes = 2 * a.numel() * a.element_size()
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "ms": round(t, 4), "gbs": round(nbytes / (t * 1e-3) / 1e9, 1)}
 
 
 def main():
@@ -63,6 +109,8 @@ def main():
     tzz, tx = to_gate_angles(g, b, "paper")
     stream = torch.cuda.current_stream()
 
+    copy = copy_calibration(torch)
+    log(f"device copy of {copy['bytes'] / 2 ** 30:.0f} GiB: {copy['gbs']} GB/s")
     log(f"setup: n={n} p={p} c64 state {2 ** n * 8 / 2 ** 30:.0f} GiB + diag {2 ** n * 4 / 2 ** 30:.0f} GiB")
     sim = Simulator(w, "c64")
     sim.lam = torch.empty_like(sim.psi)
@@ -114,15 +162,22 @@ def main():
     shots_host = res["shots"].cpu().numpy()
     r_shots = sim.shots_ratio(shots_host)
 
-    # dominant kernel kind by total event time inside the timed steps
-    dom = max(prof, key=lambda k: prof[k][1])
-    launches, ms, by = prof[dom]
+    # dominant kernel (symbol) by total event time inside the timed steps;
+    # kinds that share a kernel are combined
+    by_kernel = {}
+    for kind, (cnt, ms, by) in prof.items():
+        k = Q.KIND_KERNEL[kind]
+        c0, m0, b0 = by_kernel.get(k, (0, 0.0, 0.0))
+        by_kernel[k] = (c0 + cnt, m0 + ms, b0 + by)
+    dom = max(by_kernel, key=lambda k: by_kernel[k][1])
+    launches, ms, by = by_kernel[dom]
     avg_ms = ms / max(launches, 1)
-    achieved = (by / max(launches, 1)) / (avg_ms * 1e-3) / 1e9
+    bpl = by / max(launches, 1)
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "launches": launches, "avg_launch_ms": round(avg_ms, 4),
-                "bytes_per_launch": by / max(launches, 1)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                "launches": launches, "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bpl,
+                "copy_ceiling_gbs": copy["gbs"], "frac_of_copy": round(achieved / copy["gbs"], 4)}
     per_kind = {k: {"launches": v[0], "ms_total": round(v[1], 3),
                     "gbs": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                 for k, v in prof.items() if v[0] > 0}
@@ -145,6 +200,7 @@ def main():
         "breakdown_ms": {"cost_diagonal": round(float(t_diag), 3), "forward_with_readout": round(float(t_fwd), 3),
                          "sample": round(float(t_smp), 3), "forward_plus_adjoint": round(float(t_adj), 3)},
         "fwd_adjoint_over_fwd": round(float(t_adj / t_fwd), 3),
+        "device_copy": copy,
         "forward_useful_hbm_frac": round(alg_fwd / (t_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "kernels": per_kind,

@@ -172,15 +172,16 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
  * bytes (the bytes each launch must move at minimum).  Enabling clears.
  */
 typedef enum {
-    QS_KIND_PASS = 0,        /* mixer pass kernels (state read + write) */
-    QS_KIND_PASS_PHASE = 1,  /* mixer pass kernels that also apply a cost phase */
-    QS_KIND_ADJOINT = 2,     /* reverse-sweep kernels (two vectors) */
+    QS_KIND_PASS = 0,        /* forward tile passes without a cost phase */
+    QS_KIND_PASS_PHASE = 1,  /* forward tile passes that also apply a cost phase (same kernel) */
+    QS_KIND_ADJOINT = 2,     /* reverse-sweep passes (two vectors) */
     QS_KIND_EXPECT = 3,      /* stand-alone <C>/norm readout */
     QS_KIND_SAMPLE = 4,      /* sampling kernels */
     QS_KIND_ELEMENTWISE = 5, /* init and stand-alone cost-layer kernels */
     QS_KIND_REDUCE = 6,      /* small reductions of per-workgroup partials */
     QS_KIND_SMALL = 7,       /* single-workgroup kernels for states of <= 8192 amplitudes */
-    QS_KIND_COUNT = 8
+    QS_KIND_TURNAROUND = 8,  /* the pass where the forward sweep turns into the reverse sweep */
+    QS_KIND_COUNT = 9
 } qs_kernel_kind;
 
 qs_status qs_profile(qs_state s, int enable);

@@ -411,7 +411,7 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
         const KSpec &k = ks.back();
         PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
         pp.lam = lam;
-        if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_ADJOINT, dim * (ab + 4 + ab), &grid, where))
+        if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_TURNAROUND, dim * (ab + 4 + ab), &grid, where))
             return st;
         const int map[kSlots] = {2 + cc.p + k.post, 0, 1, -1};
         if (qs_status st = run_reduce(s, grid, map, 1, where)) return st;

@@ -29,7 +29,7 @@ namespace {
 // W_t < 2^31 at most five.  Entries are evaluated once per workgroup with
 // FP64 arguments reduced modulo 2 pi.
 #ifndef QS_ADJ_PREFETCH
-#define QS_ADJ_PREFETCH 0
+#define QS_ADJ_PREFETCH 1
 #endif
 
 constexpr int kTabLevels = 5;
@@ -287,14 +287,22 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
         if (tile < pp.ntiles) fetch(tile, p, l);
 #endif
         for (; tile < pp.ntiles; tile += G) {
+            const Geom gg = geom_of(pp);
+            const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+            int cur = opaque(pp.load_win);
+            // this tile's diagonal is requested before the next tile's vectors:
+            // memory counters retire in order, so the phase step then waits
+            // only for these loads
+            int32_t dg[NR];
+            if (pp.has_phase) {
+                const int pw = opaque(pp.phase_win);
+                for_each_reg<NR>(win_addr(tid, pw, RB, base, gg.c, gg.q0), [&](int r, int64_t g) { dg[r] = diag[g]; });
+            }
 #if QS_ADJ_PREFETCH
             if (tile + G < pp.ntiles) fetch(tile + G, np, nl);
 #else
             fetch(tile, p, l);
 #endif
-            const Geom gg = geom_of(pp);
-            const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
-            int cur = opaque(pp.load_win);
             if (pp.has_post) {
                 unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.post, cur, tid, acc[0]);
                 if (pp.post.tan) {
@@ -306,8 +314,9 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
                 }
             }
             if (pp.has_phase) {
-                for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
-                    const int32_t C = diag[g];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    const int32_t C = dg[r];
                     const R im = l[r].x * p[r].y - l[r].y * p[r].x;
                     acc[1] += -0.2 * (double)C * (double)im;
                     if (!pp.init) {
@@ -315,7 +324,7 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
                         p[r] = cmul(p[r], f);
                         l[r] = cmul(l[r], f);
                     }
-                });
+                }
             }
             if (pp.has_pre) {
                 unrun_stage<RB>(p, l, lds, pp.A, pp.targets, pp.pre, cur, tid, acc[2]);

@@ -22,8 +22,15 @@ QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_HIP, QS_ERR_RANGE, QS_ERR_STATE = range(6)
 QS_C64, QS_C128 = 0, 1
 QS_MAX_QUBITS_C64, QS_MAX_QUBITS_C128 = 34, 33
 (QS_KIND_PASS, QS_KIND_PASS_PHASE, QS_KIND_ADJOINT, QS_KIND_EXPECT, QS_KIND_SAMPLE,
- QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_COUNT) = range(9)
-KIND_NAMES = ["pass", "pass_phase", "adjoint", "expect", "sample", "elementwise", "reduce", "small"]
+ QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_TURNAROUND, QS_KIND_COUNT) = range(10)
+KIND_NAMES = ["pass", "pass_phase", "adjoint", "expect", "sample", "elementwise", "reduce", "small",
+              "turnaround"]
+# kernel symbol behind each kind (kinds that share a kernel are timed together
+# when compared with a profiler's per-kernel statistics)
+KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "adjoint_kernel<reverse>",
+               "turnaround": "adjoint_kernel<turnaround>", "expect": "expect_kernel",
+               "elementwise": "elementwise", "sample": "sample_kernels", "reduce": "reduce_kernels",
+               "small": "small_kernels"}
 
 # every symbol the public headers declare
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",

@@ -24,7 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2604_26423_amd/csrc/pass.hip", "paper_2604_26423_amd/csrc/device.h",
+KERNEL_SOURCES = ["paper_2604_26423_amd/csrc/pass.hip", "paper_2604_26423_amd/csrc/tiles.h",
+                  "paper_2604_26423_amd/csrc/device.h",
                   "paper_2604_26423_amd/csrc/internal.h", "paper_2604_26423_amd/csrc/plan.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 

@@ -171,6 +171,51 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
  * kind, the launch count, the summed event time and the summed algorithmic
  * bytes (the bytes each launch must move at minimum).  Enabling clears.
  */
+/*
+ * Batched circuits (target workload: hundreds of small, uneven circuits).
+ * Each circuit has its own instance, depth and angles; all of them run the
+ * forward circuit and the adjoint gradient of qs_adjoint_grad in one
+ * persistent kernel launch that hands out (circuit, pass, chunk of tiles)
+ * work items from a global queue in rounds (pass r of every circuit, largest
+ * circuits first); a work item waits for its circuit's previous pass through
+ * completion counters.  Single-circuit tile kernels and the batched kernel
+ * compute the same arithmetic.
+ */
+#define QS_BATCH_MAX_QUBITS 30
+
+typedef struct {
+    int n;                   /* qubits: more than 13 (complex64) / 12 (complex128), at most 30 */
+    int p;                   /* layers, >= 1 */
+    const int32_t *w_tenths; /* host, n(n-1)/2 weights in tenths (as qs_cost_diagonal) */
+} qs_circuit;
+
+typedef struct qs_batch_s *qs_batch;
+
+/*
+ * Allocate device memory for every circuit (state, adjoint vector, cost
+ * diagonal; one allocation) and build the cost diagonals and C(x*).
+ * The weight arrays are read during the call only.  Synchronises.
+ */
+qs_status qs_batch_create(int count, const qs_circuit *circuits, int prec, void *hip_stream, qs_batch *out);
+
+/* W_t, C(x*) (tenths) and device pointers of circuit i (all outputs nullable). */
+qs_status qs_batch_info(qs_batch b, int i, int64_t *w_total_tenths, int32_t *cmax_tenths, void **psi_dev,
+                        int32_t **diag_dev);
+
+/*
+ * Forward circuit and adjoint gradient of every circuit (as qs_adjoint_grad).
+ * theta_zz, theta_x, d_theta_zz, d_theta_x: host arrays with the circuits'
+ * per-layer values concatenated in circuit order (sum of p entries);
+ * exp_c: host array of count values.  Synchronises.
+ * Errors: QS_ERR_ARG, QS_ERR_HIP (including a dependency wait that exceeded
+ * its bound, which cannot happen while the queue drains normally).
+ */
+qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double *theta_x, double *exp_c,
+                                double *d_theta_zz, double *d_theta_x);
+
+/* Release the batch and its device memory. */
+qs_status qs_batch_free(qs_batch b);
+
 typedef enum {
     QS_KIND_PASS = 0,        /* forward tile passes without a cost phase */
     QS_KIND_PASS_PHASE = 1,  /* forward tile passes that also apply a cost phase (same kernel) */

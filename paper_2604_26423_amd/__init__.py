@@ -6,6 +6,6 @@ Nothing here falls back to a CPU implementation: without the built library
 every call raises.
 """
 from . import qs  # noqa: F401
-from .lrqaoa import Simulator, expect_c, linear_ramp, to_gate_angles, gate_grad_to_schedule  # noqa: F401
+from .lrqaoa import Batch, Simulator, expect_c, linear_ramp, to_gate_angles, gate_grad_to_schedule  # noqa: F401
 
-__all__ = ["qs", "Simulator", "expect_c", "linear_ramp", "to_gate_angles", "gate_grad_to_schedule"]
+__all__ = ["qs", "Batch", "Simulator", "expect_c", "linear_ramp", "to_gate_angles", "gate_grad_to_schedule"]

@@ -90,6 +90,21 @@ struct qs_state_s {
     std::vector<ProfRec> recs;
 };
 
+struct qs_batch_s {
+    int count = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    std::vector<int> n, p;
+    std::vector<int64_t> W, angle_off;
+    std::vector<int32_t> cmax;
+    std::vector<size_t> off_psi, off_lam, off_diag;
+    void *mem = nullptr;
+    DevBuf steps, tabs, partials, counters, results, index;
+    std::vector<qs::BatchStep> steps_h;
+    std::vector<int> idx_h;        // cstep list, then cstep offsets
+    std::vector<int64_t> res_off_h;
+    std::vector<double> res_h;
+};
+
 namespace {
 
 // ---------------------------------------------------------------- profiling
@@ -149,16 +164,17 @@ RxStage rx_stage(double theta, int m, double *factor)
     return st;
 }
 
-PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb)
+PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassGeom &g, const KSpec &k,
+                       const Circuit &cc, int tb)
 {
-    const int T = tile_bits(s->prec);
+    const int T = tile_bits(prec);
     PassProg pp{};
-    pp.psi = s->psi;
+    pp.psi = psi;
     pp.lam = nullptr;
     pp.diag = cc.diag;
-    pp.partials = (double *)s->partials.p;
-    pp.ntiles = (int64_t)1 << (s->n - T);
-    pp.n = s->n;
+    pp.partials = partials;
+    pp.ntiles = (int64_t)1 << (n - T);
+    pp.n = n;
     pp.c = g.c;
     pp.q0 = g.q0;
     pp.targets = g.targets;
@@ -185,8 +201,13 @@ PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit 
     if (pp.has_phase) pp.theta_zz = cc.tzz[k.phase];
     pp.W = cc.W;
     pp.phase_levels = phase_table_levels(cc.W);
-    pp.amp0 = sqrt(ldexp(1.0, -s->n));
+    pp.amp0 = sqrt(ldexp(1.0, -n));
     return pp;
+}
+
+PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb)
+{
+    return make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb);
 }
 
 // Launch one tile kernel over a persistent grid; returns the grid (the number
@@ -431,6 +452,57 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     return QS_OK;
 }
 
+// ---------------------------------------------------------------- diagonal helpers
+// Dense symmetric weight matrix from the lexicographic edge list, with checks.
+qs_status weight_matrix(int n, const int32_t *w, std::vector<int32_t> &wm, int64_t *W)
+{
+    const int64_t ne = (int64_t)n * (n - 1) / 2;
+    if (ne > 0 && !w) return fail(QS_ERR_ARG, "null weight array");
+    wm.assign((size_t)n * n, 0);
+    int64_t sum = 0, e = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j, ++e) {
+            const int32_t x = w[e];
+            if (x < 0 || x >= (1 << 20)) return fail(QS_ERR_ARG, "weight %lld = %d outside [0, 2^20)", (long long)e, x);
+            wm[(size_t)i * n + j] = wm[(size_t)j * n + i] = x;
+            sum += x;
+        }
+    if (sum >= ((int64_t)1 << 31)) return fail(QS_ERR_RANGE, "W_t = %lld does not fit in int32", (long long)sum);
+    *W = sum;
+    return QS_OK;
+}
+
+// Scratch for building diagonals of up to nmax qubits: weight matrix, low-bit
+// table, per-workgroup maxima (two levels) and `nres` int32 results.
+struct DiagScratch {
+    size_t off_low, off_wg, off_tmp, off_res, total;
+};
+
+DiagScratch diag_scratch_layout(int nmax, int nres)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    DiagScratch L;
+    const int64_t nwg = diag_wg_count(nmax);
+    L.off_low = up((size_t)nmax * nmax * 4);
+    L.off_wg = L.off_low + 8192 * 4;
+    L.off_tmp = L.off_wg + up((size_t)nwg * 4);
+    L.off_res = L.off_tmp + up((size_t)(nwg / 4096 + 2) * 4);
+    L.total = L.off_res + up((size_t)nres * 4);
+    return L;
+}
+
+// Queue the diagonal of one circuit; its C_max lands in result slot `res`.
+// `wm` must stay alive until the stream has run the copy.
+hipError_t build_diagonal(int n, const std::vector<int32_t> &wm, int32_t *diag, char *scratch, const DiagScratch &L,
+                          int res, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(scratch, wm.data(), (size_t)n * n * 4, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return launch_cost_diagonal(n, (const int32_t *)scratch, diag, (int32_t *)(scratch + L.off_low),
+                                (int32_t *)(scratch + L.off_wg), (int32_t *)(scratch + L.off_tmp),
+                                (int32_t *)(scratch + L.off_res) + res, st);
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -529,39 +601,18 @@ qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev, in
         if (n < 1 || n > QS_MAX_QUBITS_C64) return fail(QS_ERR_ARG, "n = %d outside 1..%d", n, QS_MAX_QUBITS_C64);
         if (!diag_dev) return fail(QS_ERR_ARG, "null diagonal buffer");
         if (!aligned(diag_dev, 16)) return fail(QS_ERR_ARG, "diagonal buffer must be 16-byte aligned");
-        const int64_t ne = (int64_t)n * (n - 1) / 2;
-        if (ne > 0 && !w_tenths) return fail(QS_ERR_ARG, "null weight array");
+        std::vector<int32_t> wm;
         int64_t W = 0;
-        std::vector<int32_t> wm((size_t)n * n, 0);
-        int64_t e = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j, ++e) {
-                const int32_t w = w_tenths[e];
-                if (w < 0 || w >= (1 << 20)) return fail(QS_ERR_ARG, "weight %lld = %d outside [0, 2^20)", (long long)e, w);
-                wm[(size_t)i * n + j] = wm[(size_t)j * n + i] = w;
-                W += w;
-            }
-        if (W >= ((int64_t)1 << 31)) return fail(QS_ERR_RANGE, "W_t = %lld does not fit in int32", (long long)W);
+        if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
         hipStream_t st = (hipStream_t)hip_stream;
-        // scratch: weight matrix, low-bit table, per-workgroup maxima (+ second level, result)
-        const int64_t nwg = diag_wg_count(n);
-        const size_t off_low = ((size_t)n * n * 4 + 255) & ~(size_t)255;
-        const size_t off_wg = off_low + 8192 * 4;
-        const size_t off_tmp = off_wg + (((size_t)nwg * 4 + 255) & ~(size_t)255);
-        const size_t off_res = off_tmp + (((size_t)(nwg / 4096 + 2) * 4 + 255) & ~(size_t)255);
-        const size_t total = off_res + 256;
+        const DiagScratch L = diag_scratch_layout(n, 1);
         char *scratch = nullptr;
-        HIPCHK(hipMalloc(&scratch, total), "qs_cost_diagonal");
-        auto cleanup = [&]() { (void)hipFree(scratch); };
-        hipError_t he = hipMemcpyAsync(scratch, wm.data(), (size_t)n * n * 4, hipMemcpyHostToDevice, st);
-        if (he == hipSuccess)
-            he = launch_cost_diagonal(n, (const int32_t *)scratch, diag_dev, (int32_t *)(scratch + off_low),
-                                      (int32_t *)(scratch + off_wg), (int32_t *)(scratch + off_tmp),
-                                      (int32_t *)(scratch + off_res), st);
+        HIPCHK(hipMalloc(&scratch, L.total), "qs_cost_diagonal");
+        hipError_t he = build_diagonal(n, wm, diag_dev, scratch, L, 0, st);
         int32_t cmax = 0;
-        if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch + off_res, 4, hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch + L.off_res, 4, hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
-        cleanup();
+        (void)hipFree(scratch);
         if (he != hipSuccess) return hip_fail(he, "qs_cost_diagonal");
         if (w_total_tenths) *w_total_tenths = W;
         if (cmax_tenths) *cmax_tenths = cmax;
@@ -767,6 +818,264 @@ qs_status qs_profile_read(qs_state s, int kind, int64_t *launches, double *total
     if (launches) *launches = cnt;
     if (total_ms) *total_ms = ms;
     if (bytes) *bytes = by;
+    return QS_OK;
+}
+
+// ---------------------------------------------------------------- batch
+qs_status qs_batch_create(int count, const qs_circuit *circuits, int prec, void *hip_stream, qs_batch *out)
+{
+    try {
+        if (!out) return fail(QS_ERR_ARG, "null output handle pointer");
+        *out = nullptr;
+        if (count < 1) return fail(QS_ERR_ARG, "count must be >= 1");
+        if (!circuits) return fail(QS_ERR_ARG, "null circuit array");
+        if (prec != QS_C64 && prec != QS_C128) return fail(QS_ERR_ARG, "bad precision %d", prec);
+        const int T = tile_bits(prec);
+        std::vector<std::vector<int32_t>> wms(count);
+        qs_batch b0 = nullptr;
+        int nmax = 0;
+        for (int i = 0; i < count; ++i) {
+            const qs_circuit &c = circuits[i];
+            if (c.n <= T || c.n > QS_BATCH_MAX_QUBITS)
+                return fail(QS_ERR_ARG, "circuit %d: n = %d outside %d..%d", i, c.n, T + 1, QS_BATCH_MAX_QUBITS);
+            if (c.p < 1) return fail(QS_ERR_ARG, "circuit %d: p must be >= 1", i);
+            int64_t W = 0;
+            if (qs_status st = weight_matrix(c.n, c.w_tenths, wms[i], &W)) return st;
+            nmax = std::max(nmax, c.n);
+        }
+        qs_batch b = new qs_batch_s();
+        b0 = b;
+        b->count = count;
+        b->prec = prec;
+        b->stream = (hipStream_t)hip_stream;
+        size_t off = 0;
+        auto place = [&](size_t bytes) {
+            const size_t o = off;
+            off += (bytes + 255) & ~(size_t)255;
+            return o;
+        };
+        int64_t aoff = 0;
+        for (int i = 0; i < count; ++i) {
+            const int n = circuits[i].n;
+            b->n.push_back(n);
+            b->p.push_back(circuits[i].p);
+            b->angle_off.push_back(aoff);
+            aoff += circuits[i].p;
+            b->off_psi.push_back(place(qs_state_bytes(n, prec)));
+            b->off_lam.push_back(place(qs_state_bytes(n, prec)));
+            b->off_diag.push_back(place(((size_t)1 << n) * 4));
+            int64_t W = 0;
+            for (size_t e = 0; e < (size_t)n * (n - 1) / 2; ++e) W += circuits[i].w_tenths[e];
+            b->W.push_back(W);
+        }
+        b->angle_off.push_back(aoff);
+        hipError_t he = hipMalloc(&b->mem, off);
+        if (he != hipSuccess) {
+            delete b0;
+            return hip_fail(he, "qs_batch_create");
+        }
+        const DiagScratch L = diag_scratch_layout(nmax, count);
+        char *scratch = nullptr;
+        he = hipMalloc(&scratch, L.total);
+        for (int i = 0; i < count && he == hipSuccess; ++i)
+            he = build_diagonal(b->n[i], wms[i], (int32_t *)((char *)b->mem + b->off_diag[i]), scratch, L, i,
+                                b->stream);
+        b->cmax.assign(count, 0);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(b->cmax.data(), scratch + L.off_res, (size_t)count * 4, hipMemcpyDeviceToHost,
+                                b->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(b->stream);
+        if (scratch) (void)hipFree(scratch);
+        if (he != hipSuccess) {
+            (void)hipFree(b->mem);
+            delete b0;
+            return hip_fail(he, "qs_batch_create");
+        }
+        *out = b;
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_OOM, "qs_batch_create: host allocation failed");
+    }
+}
+
+qs_status qs_batch_info(qs_batch b, int i, int64_t *w_total_tenths, int32_t *cmax_tenths, void **psi_dev,
+                        int32_t **diag_dev)
+{
+    if (!b) return fail(QS_ERR_ARG, "null batch handle");
+    if (i < 0 || i >= b->count) return fail(QS_ERR_ARG, "circuit index %d outside 0..%d", i, b->count - 1);
+    if (w_total_tenths) *w_total_tenths = b->W[i];
+    if (cmax_tenths) *cmax_tenths = b->cmax[i];
+    if (psi_dev) *psi_dev = (char *)b->mem + b->off_psi[i];
+    if (diag_dev) *diag_dev = (int32_t *)((char *)b->mem + b->off_diag[i]);
+    return QS_OK;
+}
+
+qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double *theta_x, double *exp_c,
+                                double *d_theta_zz, double *d_theta_x)
+{
+    try {
+        if (!b) return fail(QS_ERR_ARG, "null batch handle");
+        if (!theta_zz || !theta_x) return fail(QS_ERR_ARG, "null angle array");
+        if (!exp_c || !d_theta_zz || !d_theta_x) return fail(QS_ERR_ARG, "null output array");
+        const int64_t nang = b->angle_off.back();
+        for (int64_t k = 0; k < nang; ++k)
+            if (!std::isfinite(theta_zz[k]) || !std::isfinite(theta_x[k]))
+                return fail(QS_ERR_ARG, "non-finite angle at index %lld", (long long)k);
+        const char *where = "qs_batch_forward_grad";
+        const int T = tile_bits(b->prec);
+        const int count = b->count;
+
+        // per-circuit step lists (in the circuit's own order)
+        std::vector<std::vector<BatchStep>> cs(count);
+        for (int c = 0; c < count; ++c) {
+            const int n = b->n[c], p = b->p[c];
+            void *psi = (char *)b->mem + b->off_psi[c];
+            void *lam = (char *)b->mem + b->off_lam[c];
+            const int32_t *diag = (const int32_t *)((char *)b->mem + b->off_diag[c]);
+            const Circuit cc{diag, b->W[c], p, theta_zz + b->angle_off[c], theta_x + b->angle_off[c]};
+            const std::vector<PassGeom> geo = plan_passes(n, b->prec);
+            const std::vector<KSpec> ks = forward_specs((int)geo.size(), p);
+            auto add = [&](const KSpec &k, int kind) {
+                BatchStep s{};
+                s.pp = make_prog_raw(psi, n, b->prec, nullptr, geo[k.pass], k, cc, kBatchThreadBits);
+                s.pp.xcd_remap = 0;
+                s.kind = kind;
+                s.circuit = c;
+                for (int j = 0; j < kSlots; ++j) s.map[j] = -1;
+                if (kind >= 1) s.pp.lam = lam;
+                if (kind == 1) {
+                    s.map[0] = 2 + p + k.post;
+                    s.map[1] = 0;
+                    s.map[2] = 1;
+                } else if (kind == 2) {
+                    s.pp.load_win = s.pp.final_win;
+                    s.map[0] = k.post >= 0 ? 2 + p + k.post : -1;
+                    s.map[1] = k.phase >= 0 ? 2 + k.phase : -1;
+                    s.map[2] = k.pre >= 0 ? 2 + p + k.pre : -1;
+                }
+                const int64_t ntiles = (int64_t)1 << (n - T);
+                s.tiles_per_chunk = (int)std::min<int64_t>(ntiles, 16);
+                s.chunks = (int)((ntiles + s.tiles_per_chunk - 1) / s.tiles_per_chunk);
+                cs[c].push_back(s);
+            };
+            for (size_t i = 0; i + 1 < ks.size(); ++i) add(ks[i], 0);
+            add(ks.back(), 1);
+            for (int i = (int)ks.size() - 2; i >= 0; --i) add(ks[i], 2);
+        }
+        // rounds: step r of every circuit, the largest circuits first
+        std::vector<int> order(count);
+        for (int c = 0; c < count; ++c) order[c] = c;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const double wx = ldexp((double)cs[x].size(), b->n[x]), wy = ldexp((double)cs[y].size(), b->n[y]);
+            return wx > wy;
+        });
+        size_t maxsteps = 0;
+        for (int c = 0; c < count; ++c) maxsteps = std::max(maxsteps, cs[c].size());
+        b->steps_h.clear();
+        std::vector<std::vector<int>> where_c(count);
+        std::vector<int> last(count, -1);
+        int64_t items = 0, tabs = 0;
+        const int tabn = batch_table_entries();
+        for (size_t r = 0; r < maxsteps; ++r)
+            for (int c : order) {
+                if (r >= cs[c].size()) continue;
+                BatchStep s = cs[c][r];
+                s.prev = last[c];
+                s.item0 = items;
+                items += s.chunks;
+                s.tab_off = s.pp.has_phase ? (tabs++) * tabn : -1;
+                last[c] = (int)b->steps_h.size();
+                where_c[c].push_back(last[c]);
+                b->steps_h.push_back(s);
+            }
+        const int nsteps = (int)b->steps_h.size();
+        b->idx_h.clear();
+        std::vector<int> coff(count + 1, 0);
+        for (int c = 0; c < count; ++c) {
+            coff[c] = (int)b->idx_h.size();
+            for (int j : where_c[c]) b->idx_h.push_back(j);
+        }
+        coff[count] = (int)b->idx_h.size();
+        const int nidx = (int)b->idx_h.size();
+        b->idx_h.insert(b->idx_h.end(), coff.begin(), coff.end());
+        b->res_off_h.assign(count + 1, 0);
+        for (int c = 0; c < count; ++c) b->res_off_h[c + 1] = b->res_off_h[c] + 2 + 2 * b->p[c];
+        const int64_t nres = b->res_off_h[count];
+
+        const size_t ab = b->prec == QS_C64 ? 8 : 16;
+        HIPCHK(b->steps.ensure(sizeof(BatchStep) * nsteps), where);
+        HIPCHK(b->tabs.ensure((size_t)std::max<int64_t>(tabs, 1) * tabn * ab), where);
+        HIPCHK(b->partials.ensure((size_t)items * kSlots * sizeof(double)), where);
+        // counters: ticket (8 B), abort flag, per-step done counters
+        const size_t cnt_doubles = (16 + (size_t)nsteps * 4 + 7) / 8;
+        HIPCHK(b->counters.ensure(cnt_doubles * 8), where);
+        HIPCHK(b->results.ensure((size_t)nres * sizeof(double)), where);
+        HIPCHK(b->index.ensure(b->idx_h.size() * sizeof(int) + 64 + b->res_off_h.size() * sizeof(int64_t)), where);
+        char *idx_d = (char *)b->index.p;
+        const size_t roff_pos = (b->idx_h.size() * sizeof(int) + 63) & ~(size_t)63;
+        HIPCHK(hipMemcpyAsync(b->steps.p, b->steps_h.data(), sizeof(BatchStep) * nsteps, hipMemcpyHostToDevice,
+                              b->stream), where);
+        HIPCHK(hipMemcpyAsync(idx_d, b->idx_h.data(), b->idx_h.size() * sizeof(int), hipMemcpyHostToDevice, b->stream),
+               where);
+        HIPCHK(hipMemcpyAsync(idx_d + roff_pos, b->res_off_h.data(), b->res_off_h.size() * sizeof(int64_t),
+                              hipMemcpyHostToDevice, b->stream), where);
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((cnt_doubles + 255) / 256)), dim3(256), 0, b->stream,
+                           (double *)b->counters.p, (int)cnt_doubles);
+        HIPCHK(hipGetLastError(), where);
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((nres + 255) / 256)), dim3(256), 0, b->stream,
+                           (double *)b->results.p, (int)nres);
+        HIPCHK(hipGetLastError(), where);
+        HIPCHK(launch_batch_tables(b->prec, (const BatchStep *)b->steps.p, nsteps, b->tabs.p, b->stream), where);
+        BatchArgs args{};
+        args.steps = (const BatchStep *)b->steps.p;
+        args.nsteps = nsteps;
+        args.nitems = items;
+        args.ticket = (unsigned long long *)b->counters.p;
+        args.abort_flag = (int *)((char *)b->counters.p + 8);
+        args.done = (unsigned *)((char *)b->counters.p + 16);
+        args.partials = (double *)b->partials.p;
+        args.tabs = b->tabs.p;
+        args.spin_limit = 4000000;
+        HIPCHK(launch_batch(b->prec, args, batch_grid(b->prec), b->stream), where);
+        HIPCHK(launch_batch_reduce((const BatchStep *)b->steps.p, (const int *)idx_d, (const int *)idx_d + nidx,
+                                   (const int64_t *)(idx_d + roff_pos), (const double *)b->partials.p,
+                                   (double *)b->results.p, count, b->stream),
+               where);
+        b->res_h.assign(nres, 0.0);
+        int32_t abort_flag = 0;
+        HIPCHK(hipMemcpyAsync(b->res_h.data(), b->results.p, (size_t)nres * sizeof(double), hipMemcpyDeviceToHost,
+                              b->stream), where);
+        HIPCHK(hipMemcpyAsync(&abort_flag, args.abort_flag, 4, hipMemcpyDeviceToHost, b->stream), where);
+        HIPCHK(hipStreamSynchronize(b->stream), where);
+        if (abort_flag) return fail(QS_ERR_HIP, "%s: a work item waited too long for its predecessor", where);
+        for (int c = 0; c < count; ++c) {
+            const double *r = b->res_h.data() + b->res_off_h[c];
+            const int p = b->p[c];
+            exp_c[c] = (r[1] / 10.0) / r[0];
+            for (int k = 0; k < p; ++k) {
+                d_theta_zz[b->angle_off[c] + k] = r[2 + k] / r[0];
+                d_theta_x[b->angle_off[c] + k] = r[2 + p + k] / r[0];
+            }
+        }
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_OOM, "qs_batch_forward_grad: host allocation failed");
+    }
+}
+
+qs_status qs_batch_free(qs_batch b)
+{
+    if (!b) return QS_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    else (void)hipDeviceSynchronize();
+    if (b->mem) (void)hipFree(b->mem);
+    b->steps.release();
+    b->tabs.release();
+    b->partials.release();
+    b->counters.release();
+    b->results.release();
+    b->index.release();
+    delete b;
     return QS_OK;
 }
 

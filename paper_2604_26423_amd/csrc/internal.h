@@ -118,6 +118,46 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
 // Grid of a tile kernel (kind 0 = forward, 1 = turnaround, 2 = reverse pass).
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles);
 
+// ---- batched circuits: one persistent launch over a ticket queue ----
+constexpr int kBatchThreadBits = 9;   // batched tile kernels: 512 threads
+
+// One pass of one circuit.  Its tiles are split into `chunks` work items; the
+// items of all steps are numbered in rounds (step r of every circuit that has
+// one), largest circuits first, and workgroups claim them in that order.
+struct BatchStep {
+    PassProg pp;
+    int kind;             // 0 = forward pass, 1 = turnaround, 2 = reverse pass
+    int circuit;
+    int prev;             // previous step of the same circuit, -1 if none
+    int chunks;           // work items of this step
+    int tiles_per_chunk;
+    int map[kSlots];      // accumulator index of each partial-sum slot (-1: unused)
+    int64_t item0;        // first item number of this step
+    int64_t tab_off;      // offset of this step's phase table (entries), -1 if none
+};
+
+struct BatchArgs {
+    const BatchStep *steps;
+    int nsteps;
+    int64_t nitems;
+    unsigned long long *ticket;  // next item to claim
+    unsigned *done;              // finished items per step
+    int *abort_flag;             // set when a dependency wait exceeds spin_limit
+    double *partials;            // kSlots doubles per item
+    void *tabs;                  // phase tables (float2 / double2)
+    int64_t spin_limit;
+};
+
+hipError_t launch_batch_tables(int prec, const BatchStep *steps, int nsteps, void *tabs, hipStream_t st);
+hipError_t launch_batch(int prec, const BatchArgs &a, int64_t grid, hipStream_t st);
+int64_t batch_grid(int prec);
+// Fixed-order per-circuit reduction: for circuit c, res[res_off[c] + map[k]] +=
+// sum over its steps' items of slot k (steps listed in cstep[cstep_off[c]..]).
+hipError_t launch_batch_reduce(const BatchStep *steps, const int *cstep, const int *cstep_off,
+                               const int64_t *res_off, const double *partials, double *res, int ncircuits,
+                               hipStream_t st);
+int batch_table_entries();
+
 // Single-workgroup kernels for n <= T: a chunk of up to kSmallMaxLayers layers.
 struct SmallProg {
     void *psi;

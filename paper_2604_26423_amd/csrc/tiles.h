@@ -1,0 +1,329 @@
+// Tile-level device code shared by the single-circuit pass kernels and the
+// batched kernel: phase tables, butterfly stages, and the bodies that process
+// one tile of a forward pass, of the turnaround pass and of a reverse pass.
+//
+// A layer of the circuit (arXiv:2604.26423, Sec. II-B) is the cost unitary of
+// eq. (2), a diagonal phase exp(-i theta_zz (W - 2C(x))/20) once the
+// n(n-1)/2 commuting RZZ gates are combined, followed by the mixer of
+// eq. (3), RX(theta_x) on every qubit.  The RX gates commute, so one pass over
+// memory applies all of them for the T qubits of a tile: a tile of 2^T
+// amplitudes sits in registers (2^(T-TB) per thread of a 2^TB-thread
+// workgroup), butterflies act on the tile bits held in registers, and LDS
+// exchanges rotate other tile bits into registers.  The cost phase is
+// elementwise, so it is applied inside a pass, between the butterflies of one
+// layer and the next (the "pre" and "post" stages).
+#pragma once
+
+#include "device.h"
+
+namespace qs {
+
+// Phase factor of the cost layer for cut value C (tenths):
+//   exp(-i theta (W - 2C)/20) = G * prod_j T_j[d_j],  C = sum_j d_j 64^j,
+// with T_j[d] = exp(i theta d 64^j / 10) and G = f exp(-i theta W / 20)
+// folded into T_0 (f: real factor of the kernel's tangent-form stages).  The
+// digits are 6 bits wide except the top one, which takes up to 7 bits, so
+// W_t < 2^13 needs two levels (one complex multiply per amplitude) and
+// W_t < 2^31 at most five.  Entries are evaluated once per workgroup with
+// FP64 arguments reduced modulo 2 pi.
+constexpr int kTabLevels = 5;
+constexpr int kTabMax = 64 * (kTabLevels - 1) + 128;
+
+// Levels needed for cut values up to W: level j < L-1 holds 64 entries at
+// offset 64 j, the top level L-1 holds 128 entries at offset 64 (L-1); L levels
+// cover 6 (L-1) + 7 bits.
+__host__ __device__ __forceinline__ int phase_levels(int64_t W)
+{
+    int L = 1;
+    while (L < kTabLevels && (W >> (6 * (L - 1) + 7)) != 0) ++L;
+    return L;
+}
+
+template <typename V>
+__device__ __forceinline__ void build_phase_table(V *tab, int levels, double theta, int64_t W, double f, int tid,
+                                                  int nthreads)
+{
+    using R = typename Real<V>::T;
+    const int top = 64 * (levels - 1);
+    for (int i = tid; i < top + 128; i += nthreads) {
+        const int j = i < top ? (i >> 6) : levels - 1;
+        const int d = i - 64 * j;
+        const double a = theta * (double)d * (double)((int64_t)1 << (6 * j)) / 10.0;
+        V t = expi<V>(j == 0 ? a - theta * (double)W / 20.0 : a);
+        if (j == 0) t = scale_v(t, (R)f);
+        tab[i] = t;
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ V phase_factor(const V *tab, int levels, int32_t C)
+{
+    // C is in [0, W] for a matching diagonal; digits are masked so that any
+    // other input stays inside the table
+    const uint32_t u = (uint32_t)C;
+    V f = tab[u & (levels == 1 ? 127u : 63u)];
+    for (int j = 1; j < levels; ++j) {
+        const uint32_t d = (u >> (6 * j)) & (j == levels - 1 ? 127u : 63u);
+        f = cmul(f, tab[64 * j + d]);
+    }
+    return f;
+}
+
+template <typename V>
+__device__ __forceinline__ V conj_v(V a) { return V{a.x, -a.y}; }
+
+// Hide a uniform value from loop-invariant code motion: without this the
+// compiler keeps every per-register offset of the persistent loop live in
+// scalar registers for the whole kernel and spills them.
+__device__ __forceinline__ int opaque(int x)
+{
+    x = __builtin_amdgcn_readfirstlane(x);  // uniform by construction
+    asm volatile("" : "+s"(x));
+    return x;
+}
+
+struct Geom {
+    int c, q0, m;
+};
+
+__device__ __forceinline__ Geom geom_of(const PassProg &pp)
+{
+    return Geom{opaque(pp.c), opaque(pp.q0), opaque(pp.width)};
+}
+
+// Call f(r, global index) for every register r of the window.
+template <int NR, typename F>
+__device__ __forceinline__ void for_each_reg(const Addr &a, F &&f)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r) f(r, a.fast_idx(r));
+}
+
+// Forward butterfly stage: walk the windows of `seq`, applying RX to each
+// target bit once, in the first window that holds it.
+template <int RB, typename V, int NR>
+__device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq, uint32_t targets,
+                                          const RxStage &st, int &cur, int tid)
+{
+    uint32_t done = 0;
+    for (int i = 0; i < seq.cnt; ++i) {
+        const int w = seq.s[i];
+        if (w != cur) {
+            exchange<RB>(v, lds, cur, w, tid);
+            cur = w;
+        }
+        const uint32_t mask = targets & (((1u << RB) - 1u) << w) & ~done;
+        stage_rx(v, mask >> w, st, 1);
+        done |= mask;
+    }
+}
+
+// Reverse stage on psi and lambda together: windows in reverse order; for each
+// target qubit accumulate Im <lam| X_q |psi> (invariant under RX applied to
+// both), then apply RX(-theta) to both.  In tangent form both vectors carry
+// 1/cos^j after j qubits, so the terms are rescaled by cos^(2j).
+template <int RB, typename V, int NR>
+__device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
+                                            uint32_t targets, const RxStage &st, int &cur, int tid, double &gx)
+{
+    uint32_t done = 0;
+    double sc = 1.0;
+    const double c2 = st.tan ? st.c * st.c : 1.0;
+    for (int i = seq.cnt - 1; i >= 0; --i) {
+        const int w = seq.s[i];
+        if (w != cur) {
+            exchange<RB>(p, lds, cur, w, tid);
+            exchange<RB>(l, lds, cur, w, tid);
+            cur = w;
+        }
+        const uint32_t mask = targets & (((1u << RB) - 1u) << w) & ~done;
+        gx += sc * imx_reg_mask(l, p, mask >> w);
+        stage_rx(p, mask >> w, st, -1);
+        stage_rx(l, mask >> w, st, -1);
+        for (uint32_t b = mask; b; b &= b - 1) sc *= c2;
+        done |= mask;
+    }
+}
+
+template <typename V, int T, int TB> struct TileCfg {
+    using R = typename Real<V>::T;
+    static constexpr int NT = 1 << TB, RB = T - TB, NR = 1 << RB;
+};
+
+// Copy a phase table built in global memory into LDS.
+template <typename V>
+__device__ __forceinline__ void load_phase_table(V *tab, const V *src, int levels, int tid, int nthreads)
+{
+    const int n = 64 * (levels - 1) + 128;
+    for (int i = tid; i < n; i += nthreads) tab[i] = src[i];
+}
+
+// Forward pass on one tile; with pp.readout, acc += (sum |a|^2, sum |a|^2 C_t).
+template <typename V, int T, int TB>
+__device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *lds, const V *tab, double (&acc)[2],
+                                         int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    using R = typename Cfg::R;
+    constexpr int RB = Cfg::RB, NR = Cfg::NR;
+    V *psi = reinterpret_cast<V *>(pp.psi);
+    const int32_t *diag = pp.diag;
+    const bool need_diag = pp.has_phase || pp.readout;
+    const int dwin = pp.has_phase ? pp.phase_win : pp.final_win;
+    const Geom g = geom_of(pp);
+    const int64_t base = tile_base(tile, g.c, g.q0, g.m);
+    V v[NR];
+    int32_t dg[NR];
+    // the diagonal is loaded first so that its latency overlaps stage A
+    if (need_diag)
+        for_each_reg<NR>(win_addr(tid, opaque(dwin), RB, base, g.c, g.q0), [&](int r, int64_t x) { dg[r] = diag[x]; });
+    int cur = opaque(pp.load_win);
+    if (pp.init) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = V{(R)pp.amp0, (R)0};
+    } else {
+        for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
+    }
+    if (pp.has_pre) run_stage<RB>(v, lds, pp.A, pp.targets, pp.pre, cur, tid);
+    if (pp.has_phase) {
+        const int levels = pp.phase_levels;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], phase_factor<V>(tab, levels, dg[r]));
+    }
+    if (pp.has_post) run_stage<RB>(v, lds, pp.B, pp.targets, pp.post, cur, tid);
+    if (!pp.has_phase && pp.factor != 1.0) {
+        const R fac = (R)pp.factor;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = scale_v(v[r], fac);
+    }
+    if (pp.readout) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double pr = (double)v[r].x * (double)v[r].x + (double)v[r].y * (double)v[r].y;
+            acc[0] += pr;
+            acc[1] += pr * (double)dg[r];
+        }
+    }
+    for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { psi[x] = v[r]; });
+}
+
+// Turnaround on one tile: apply the last forward pass, read out the norm and
+// sum |a|^2 C_t (acc[1], acc[2]), form lambda = C psi, undo the pass on both
+// vectors (acc[0] += gx of the pass's layer) and store lambda only.
+template <typename V, int T, int TB>
+__device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *lds, double (&acc)[kSlots], int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    using R = typename Cfg::R;
+    constexpr int RB = Cfg::RB, NR = Cfg::NR;
+    const V *psi = reinterpret_cast<const V *>(pp.psi);
+    V *lam = reinterpret_cast<V *>(pp.lam);
+    const int32_t *diag = pp.diag;
+    const R fpost = (R)pp.fpost;
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    V p[NR], l[NR];
+    int cur = opaque(pp.load_win);
+    for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) { p[r] = psi[g]; });
+    run_stage<RB>(p, lds, pp.B, pp.targets, pp.post, cur, tid);
+    for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
+        const int32_t C = diag[g];
+        p[r] = scale_v(p[r], fpost);
+        const double pr = (double)p[r].x * (double)p[r].x + (double)p[r].y * (double)p[r].y;
+        acc[1] += pr;
+        acc[2] += pr * (double)C;
+        l[r] = scale_v(p[r], (R)((double)C * 0.1));
+    });
+    unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.post, cur, tid, acc[0]);
+    for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
+                     [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
+}
+
+// Reverse pass, loads: psi and lambda of a tile in the pass's load layout, and
+// the diagonal in the layout of the phase step.
+template <typename V, int T, int TB>
+__device__ __forceinline__ void rev_load_vectors(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
+                                                 V (&l)[TileCfg<V, T, TB>::NR], int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    const V *psi = reinterpret_cast<const V *>(pp.psi);
+    const V *lam = reinterpret_cast<const V *>(pp.lam);
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.load_win), Cfg::RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
+        p[r] = psi[g];
+        l[r] = lam[g];
+    });
+}
+
+template <typename V, int T, int TB>
+__device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, int32_t (&dg)[TileCfg<V, T, TB>::NR],
+                                              int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.phase_win), Cfg::RB, base, gg.c, gg.q0),
+                          [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
+}
+
+// Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
+// gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
+// first forward pass (init) only accumulates and writes nothing.
+template <typename V, int T, int TB>
+__device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
+                                         V (&l)[TileCfg<V, T, TB>::NR], const int32_t (&dg)[TileCfg<V, T, TB>::NR],
+                                         V *lds, const V *tab, double (&acc)[kSlots], int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    using R = typename Cfg::R;
+    constexpr int RB = Cfg::RB, NR = Cfg::NR;
+    V *psi = reinterpret_cast<V *>(pp.psi);
+    V *lam = reinterpret_cast<V *>(pp.lam);
+    const R fpre = (R)pp.fpre, fpost = (R)pp.fpost;
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    int cur = opaque(pp.load_win);
+    if (pp.has_post) {
+        unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.post, cur, tid, acc[0]);
+        if (pp.post.tan) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                p[r] = scale_v(p[r], fpost);
+                l[r] = scale_v(l[r], fpost);
+            }
+        }
+    }
+    if (pp.has_phase) {
+        const int levels = pp.phase_levels;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int32_t C = dg[r];
+            const R im = l[r].x * p[r].y - l[r].y * p[r].x;
+            acc[1] += -0.2 * (double)C * (double)im;
+            if (!pp.init) {
+                const V f = conj_v(phase_factor<V>(tab, levels, C));
+                p[r] = cmul(p[r], f);
+                l[r] = cmul(l[r], f);
+            }
+        }
+    }
+    if (pp.has_pre) {
+        unrun_stage<RB>(p, l, lds, pp.A, pp.targets, pp.pre, cur, tid, acc[2]);
+        if (pp.pre.tan) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                p[r] = scale_v(p[r], fpre);
+                l[r] = scale_v(l[r], fpre);
+            }
+        }
+    }
+    if (!pp.init) {
+        for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
+            psi[g] = p[r];
+            lam[g] = l[r];
+        });
+    }
+}
+
+}  // namespace qs

@@ -197,3 +197,41 @@ def expect_c(gammas, betas, sim: Simulator, convention: str = "paper"):
     if _ExpectC is None:
         _ExpectC = _autograd()
     return _ExpectC.apply(gammas, betas, sim, convention)
+
+
+class Batch:
+    """Many LR-QAOA circuits (own instance, depth and angles each) whose forward
+    circuits and adjoint gradients run in one persistent kernel launch."""
+
+    def __init__(self, instances, precision: str = "c64", stream=None):
+        """instances: sequence of (w_tenths, p)."""
+        import torch
+        self.prec = PRECISIONS[precision]
+        self.p = [int(p) for _, p in instances]
+        self.n = [n_from_edges(len(w)) for w, _ in instances]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = _qs.qs_batch_create([(n, p, w) for n, (w, p) in zip(self.n, instances)], self.prec,
+                                          self.stream)
+        info = [_qs.qs_batch_info(self.handle, i) for i in range(len(self.n))]
+        self.w_total = [x[0] for x in info]
+        self.cmax = [x[1] for x in info]
+        self.offsets = np.concatenate([[0], np.cumsum(self.p)])
+
+    def forward_grad(self, theta_zz_list, theta_x_list):
+        """Per-circuit gate angles -> (exp_c array, list of d_theta_zz, list of d_theta_x)."""
+        tzz = np.concatenate([np.asarray(t, dtype=np.float64) for t in theta_zz_list])
+        tx = np.concatenate([np.asarray(t, dtype=np.float64) for t in theta_x_list])
+        e, gzz, gx = _qs.qs_batch_forward_grad(self.handle, tzz, tx, len(self.n))
+        o = self.offsets
+        return e, [gzz[o[i]:o[i + 1]] for i in range(len(self.n))], [gx[o[i]:o[i + 1]] for i in range(len(self.n))]
+
+    def close(self):
+        if self.handle is not None:
+            _qs.qs_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,7 +36,12 @@ KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "a
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
            "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_apply_cost_layer", "qs_apply_mixer",
            "qs_forward", "qs_expect", "qs_sample", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
-           "qs_plan_check"]
+           "qs_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad", "qs_batch_free"]
+QS_BATCH_MAX_QUBITS = 30
+
+
+class QSCircuit(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("w_tenths", ctypes.c_void_p)]
 
 
 class QSError(RuntimeError):
@@ -81,6 +86,10 @@ def lib() -> ctypes.CDLL:
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
         "qs_plan_check": ([i32, i32, i32, ctypes.c_char_p, sz], i32),
+        "qs_batch_create": ([i32, vp, i32, vp, ctypes.POINTER(vp)], i32),
+        "qs_batch_info": ([vp, i32, _c_i64_p, _c_i32_p, ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
+        "qs_batch_forward_grad": ([vp, vp, vp, vp, vp, vp], i32),
+        "qs_batch_free": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -230,3 +239,41 @@ def qs_plan_check(n: int, prec: int, p: int) -> tuple:
     buf = ctypes.create_string_buffer(512)
     rc = lib().qs_plan_check(n, prec, p, buf, 512)
     return int(rc), buf.value.decode()
+
+
+# ---------------------------------------------------------------- batch
+def qs_batch_create(circuits, prec: int, stream=None) -> ctypes.c_void_p:
+    """circuits: sequence of (n, p, w_tenths)."""
+    arr = (QSCircuit * len(circuits))()
+    keep = []
+    for i, (n, p, w) in enumerate(circuits):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.int32))
+        keep.append(w)
+        arr[i] = QSCircuit(int(n), int(p), w.ctypes.data if w.size else None)
+    h = ctypes.c_void_p()
+    _check(lib().qs_batch_create(len(circuits), ctypes.cast(arr, ctypes.c_void_p), prec, _stream(stream),
+                                 ctypes.byref(h)))
+    return h
+
+
+def qs_batch_info(b, i: int) -> tuple:
+    """(W_t, C_max tenths, psi device address, diagonal device address) of circuit i."""
+    W, cm, ps, dg = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib().qs_batch_info(b, i, ctypes.byref(W), ctypes.byref(cm), ctypes.byref(ps), ctypes.byref(dg)))
+    return int(W.value), int(cm.value), int(ps.value or 0), int(dg.value or 0)
+
+
+def qs_batch_forward_grad(b, theta_zz, theta_x, count: int) -> tuple:
+    """Concatenated per-circuit angles -> (exp_c[count], d_theta_zz, d_theta_x)."""
+    tzz, tx = _f64(theta_zz), _f64(theta_x)
+    if tzz.shape != tx.shape:
+        raise ValueError("theta_zz and theta_x must have the same length")
+    e = np.empty(count)
+    gzz, gx = np.empty_like(tzz), np.empty_like(tx)
+    _check(lib().qs_batch_forward_grad(b, tzz.ctypes.data, tx.ctypes.data, e.ctypes.data, gzz.ctypes.data,
+                                       gx.ctypes.data))
+    return e, gzz, gx
+
+
+def qs_batch_free(b) -> None:
+    _check(lib().qs_batch_free(b))

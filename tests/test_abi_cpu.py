@@ -125,3 +125,17 @@ def test_pass_plan(prec):
             rc, msg = qs.qs_plan_check(n, prec, p)
             assert rc == 0, (n, p, msg)
     assert qs.qs_plan_check(0, prec, 1)[0] == 2
+
+
+def test_batch_validation():
+    w14 = np.ones(14 * 13 // 2, dtype=np.int32)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [], qs.QS_C64, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(13, 3, np.ones(78, dtype=np.int32))], qs.QS_C64, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(31, 3, np.ones(465, dtype=np.int32))], qs.QS_C64, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(14, 0, w14)], qs.QS_C64, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(14, 2, w14)], 5, 0)
+    bad = w14.copy()
+    bad[3] = -2
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(14, 2, w14), (14, 2, bad)], qs.QS_C64, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_batch_info, None, 0)
+    assert qs.lib().qs_batch_forward_grad(None, None, None, None, None, None) == qs.QS_ERR_ARG

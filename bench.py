@@ -12,7 +12,10 @@ Also reported: the same forward in complex128, the forward+adjoint / forward
 time ratio, HBM bandwidth of the dominant kernel against the 8 TB/s peak,
 and the CPU oracle timed on the host (a bounded sample, see cpu_baseline).
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c128]
+With --sweep30 the line also carries the 30-qubit depth sweep (K_30, seed 5,
+p = 3, 6, 10, 50, 100): forward and forward+adjoint times and r per depth.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c128] [--sweep30]
 """
 import argparse
 import json
@@ -77,6 +80,39 @@ def copy_calibration(torch, gib: int = 4):
     return {"bytes": nbytes, "ms": round(t, 4), "gbs": round(nbytes / (t * 1e-3) / 1e9, 1)}
 
 
+def sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream):
+    """Forward and forward+adjoint at n = 30 for each depth of the sweep."""
+    rows = []
+    sim = None
+    for run in workloads.SWEEP30:
+        if sim is None:
+            sim = Simulator(run.weights(), "c64")
+        g, b = linear_ramp(run.p, run.delta_gamma, run.delta_beta, "midpoint")
+        tzz, tx = to_gate_angles(g, b, "paper")
+        tf, ta = [], []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e2 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            e, _ = sim.forward(tzz, tx)
+            e1.record(stream)
+            sim.adjoint(tzz, tx)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            tf.append(e0.elapsed_time(e1))
+            ta.append(e1.elapsed_time(e2))
+        t_fwd, t_adj = min(tf[1:]), min(ta[1:])
+        row = {"p": run.p, "forward_ms": round(t_fwd, 3), "forward_plus_adjoint_ms": round(t_adj, 3),
+               "amp_layer_per_s": 2.0 ** run.n * run.p / (t_fwd * 1e-3), "r_exact": e / (sim.cmax / 10)}
+        log(f"sweep30 p={run.p}: forward {t_fwd:.1f} ms, forward+adjoint {t_adj:.1f} ms, r {row['r_exact']:.6f}")
+        rows.append(row)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,7 +123,8 @@ def main():
     ap.add_argument("--shots", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison")
-    ap.add_argument("--cpu-n", type=int, default=23, help="qubits of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=26, help="qubits of the CPU oracle sample")
+    ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the simulator does not shard the state across GPUs "
@@ -234,7 +271,16 @@ def main():
                        "c64_speedup": round(t128 / float(t_fwd), 3),
                        "exp_c": e128, "c64_exp_c_rel_err": abs(res["exp_c"] - e128) / e128}
 
+    # the literal reading of the gate angles (same kernels, other angles)
+    tzz_l, tx_l = to_gate_angles(g, b, "literal")
+    e_lit, _ = sim.forward(tzz_l, tx_l)
+    out["results"]["r_exact_literal_convention"] = e_lit / (res["cmax"] / 10)
     sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    if args.sweep30:
+        out["sweep30"] = sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream)
 
     if not args.no_cpu:
         import oracle

@@ -148,6 +148,23 @@ qs_status qs_expect(qs_state s, const int32_t *diag_dev, double *exp_c, double *
 qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int out_on_device);
 
 /*
+ * Exact distribution of the cut value under the state: the noiseless
+ * reference distribution that Sec. II-D subsamples (mean of n_s shots and its
+ * 3-sigma threshold), without sampling noise.  In the fixed point of
+ * qs_sample,
+ *   mass[c] = sum over x with C_t[x] = c of q(x),  c = 0..nbins-1,
+ * q(x) = floor((re^2 + im^2) 2^62); a value of C_t outside 0..nbins-1 counts
+ * in bin nbins - 1, so nbins = W_t + 1 covers every cut.  Integer sums: the
+ * result is identical run to run and equal to any exact evaluation of the
+ * same rule.  The sum of mass is the sampler's T; mass / T is the probability.
+ * mass: nbins uint64 values, on the device if out_on_device (8-byte aligned),
+ * else on the host.  One pass over the state and the diagonal.
+ * Errors: QS_ERR_ARG (nbins outside 1..2^24, null pointers, bad alignment),
+ * QS_ERR_STATE (the state norm is 4 or more, where the sums would overflow).
+ */
+qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, uint64_t *mass, int out_on_device);
+
+/*
  * Forward circuit plus the adjoint (reverse state-vector) gradient of
  * E = <psi_p| C |psi_p> / <psi_p|psi_p> with C(x) = C_t[x] / 10:
  *   d_theta_zz[k] = dE/dtheta_zz[k],  d_theta_x[k] = dE/dtheta_x[k]
@@ -226,7 +243,8 @@ typedef enum {
     QS_KIND_REDUCE = 6,      /* small reductions of per-workgroup partials */
     QS_KIND_SMALL = 7,       /* single-workgroup kernels for states of <= 8192 amplitudes */
     QS_KIND_TURNAROUND = 8,  /* the pass where the forward sweep turns into the reverse sweep */
-    QS_KIND_COUNT = 9
+    QS_KIND_HISTOGRAM = 9,   /* cut-value histogram */
+    QS_KIND_COUNT = 10
 } qs_kernel_kind;
 
 qs_status qs_profile(qs_state s, int enable);

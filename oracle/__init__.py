@@ -29,6 +29,7 @@ _lib = None
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 
 
 def lib():
@@ -40,6 +41,7 @@ def lib():
         L.oracle_cost_diagonal.argtypes = [ctypes.c_int, _i32p, _i32p]
         L.oracle_cut_value.argtypes = [ctypes.c_int, _i32p, ctypes.c_uint64]
         L.oracle_cut_value.restype = ctypes.c_int64
+        L.oracle_cut_values.argtypes = [ctypes.c_int, _i32p, _u64p, ctypes.c_int64, _i64p]
         L.oracle_weight_total.argtypes = [ctypes.c_int, _i32p]
         L.oracle_weight_total.restype = ctypes.c_int64
         L.oracle_cmax_direct.argtypes = [ctypes.c_int, _i32p]
@@ -53,6 +55,7 @@ def lib():
         L.oracle_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
         L.oracle_philox4x64_10.restype = None
         L.oracle_sample.argtypes = [ctypes.c_int, _f64p, ctypes.c_uint64, ctypes.c_int64, _u64p]
+        L.oracle_cost_histogram.argtypes = [ctypes.c_int, _f64p, _i32p, ctypes.c_int64, _u64p]
         L.oracle_adjoint.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p,
                                      ctypes.POINTER(ctypes.c_double), _f64p, _f64p]
         L.oracle_num_threads.restype = ctypes.c_int
@@ -87,6 +90,14 @@ def cost_diagonal(n: int, w) -> np.ndarray:
 
 def cut_value(n: int, w, x: int) -> int:
     return int(lib().oracle_cut_value(n, _w(w), int(x)))
+
+
+def cut_values(n: int, w, xs) -> np.ndarray:
+    """C_t[x] (eq. 6) for each basis state in xs."""
+    xs = np.ascontiguousarray(np.asarray(xs, dtype=np.uint64))
+    out = np.empty(len(xs), dtype=np.int64)
+    _check(lib().oracle_cut_values(n, _w(w), xs, len(xs), out), "cut_values")
+    return out
 
 
 def weight_total(w) -> int:
@@ -147,6 +158,17 @@ def sample(psi, seed: int, shots: int) -> np.ndarray:
     n = int(psi.size).bit_length() - 1
     out = np.empty(shots, dtype=np.uint64)
     _check(lib().oracle_sample(n, psi.view(np.float64), int(seed), int(shots), out), "sample")
+    return out
+
+
+def cost_histogram(psi, diag, nbins: int) -> np.ndarray:
+    """Fixed-point mass (2^62 = probability 1) of every cut value in tenths,
+    0..nbins-1; values outside fall into the last bin."""
+    p = _as_c128(psi)
+    n = int(p.size).bit_length() - 1
+    out = np.empty(int(nbins), dtype=np.uint64)
+    _check(lib().oracle_cost_histogram(n, p.view(np.float64), np.ascontiguousarray(diag, dtype=np.int32),
+                                       int(nbins), out), "cost_histogram")
     return out
 
 

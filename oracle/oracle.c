@@ -76,6 +76,15 @@ int oracle_cost_diagonal(int n, const int32_t *w, int32_t *diag)
 /* Cut value of a single basis state (for sampled checks at large n). */
 int64_t oracle_cut_value(int n, const int32_t *w, uint64_t x) { return cut_value(n, w, x); }
 
+/* Cut values of a list of basis states. */
+int oracle_cut_values(int n, const int32_t *w, const uint64_t *xs, int64_t count, int64_t *out)
+{
+    if (n < 1 || n > 64 || !w || (count > 0 && (!xs || !out))) return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; i++) out[i] = cut_value(n, w, xs[i]);
+    return 0;
+}
+
 /* Sum of the weights in tenths (W_t). */
 int64_t oracle_weight_total(int n, const int32_t *w)
 {
@@ -370,6 +379,28 @@ int oracle_sample(int n, const double *psi, uint64_t seed, int64_t shots, uint64
         out[s] = (uint64_t)a;
     }
     free(F);
+    return 0;
+}
+
+/*
+ * Exact distribution of the cut value under the state: the noiseless
+ * reference distribution of Sec. II-D without subsampling noise.  In the
+ * sampler's fixed point,
+ *   mass[c] = sum over x with C_t[x] = c of floor((re^2 + im^2) 2^62),
+ * with every value outside 0..nbins-1 counted in bin nbins - 1.
+ */
+int oracle_cost_histogram(int n, const double *psi, const int32_t *diag, int64_t nbins, uint64_t *mass)
+{
+    if (n < 1 || nbins < 1 || !psi || !diag || !mass) return 1;
+    const int64_t dim = (int64_t)1 << n;
+    for (int64_t c = 0; c < nbins; c++) mass[c] = 0;
+    for (int64_t x = 0; x < dim; x++) {
+        double re = psi[2 * x], im = psi[2 * x + 1];
+        double P = re * re + im * im;
+        int64_t c = diag[x];
+        if (c < 0 || c >= nbins) c = nbins - 1;
+        mass[c] += (uint64_t)(P * 4611686018427387904.0); /* 2^62 */
+    }
     return 0;
 }
 

@@ -6,6 +6,8 @@ Nothing here falls back to a CPU implementation: without the built library
 every call raises.
 """
 from . import qs  # noqa: F401
-from .lrqaoa import Batch, Simulator, expect_c, linear_ramp, to_gate_angles, gate_grad_to_schedule  # noqa: F401
+from .lrqaoa import (Batch, Simulator, expect_c, gate_grad_to_schedule, linear_ramp, mean_of_means,  # noqa: F401
+                     to_gate_angles)
 
-__all__ = ["qs", "Batch", "Simulator", "expect_c", "linear_ramp", "to_gate_angles", "gate_grad_to_schedule"]
+__all__ = ["qs", "Batch", "Simulator", "expect_c", "linear_ramp", "to_gate_angles", "gate_grad_to_schedule",
+           "mean_of_means"]

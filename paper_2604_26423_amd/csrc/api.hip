@@ -85,7 +85,7 @@ struct qs_state_s {
     void *psi = nullptr;
     bool own = false;
     hipStream_t stream = nullptr;
-    DevBuf partials, tmp, results, sample, shots_out, lambda;
+    DevBuf partials, tmp, results, sample, shots_out, lambda, hist;
     bool prof = false;
     std::vector<ProfRec> recs;
 };
@@ -748,6 +748,52 @@ qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int
     HIPCHK(hipStreamSynchronize(s->stream), where);
     if (flag == 1) return fail(QS_ERR_STATE, "qs_sample: state has zero norm");
     if (flag == 2) return fail(QS_ERR_STATE, "qs_sample: state norm too large (|a|^2 sums to 4 or more)");
+    return QS_OK;
+}
+
+qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, uint64_t *mass, int out_on_device)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (qs_status st = check_diag(s, diag_dev, 0)) return st;
+    if (nbins < 1 || nbins > kHistMaxBins) return fail(QS_ERR_ARG, "nbins = %d outside 1..%d", nbins, kHistMaxBins);
+    if (!mass) return fail(QS_ERR_ARG, "null output array");
+    if (out_on_device && !aligned(mass, 8)) return fail(QS_ERR_ARG, "output must be 8-byte aligned");
+    const char *where = "qs_cost_histogram";
+    const HistGeom g = hist_geom(s->prec, s->n, nbins);
+    // scratch: rows of nbins uint64, the device output, per-workgroup FP64 sums, the flag
+    const size_t o_rows = 0;
+    const size_t o_out = o_rows + (((size_t)g.rows * nbins * 8 + 255) & ~(size_t)255);
+    const size_t o_fsum = o_out + (((size_t)nbins * 8 + 255) & ~(size_t)255);
+    const size_t o_flag = o_fsum + (((size_t)g.groups * 8 + 255) & ~(size_t)255);
+    HIPCHK(s->hist.ensure(o_flag + 256), where);
+    char *base = (char *)s->hist.p;
+    uint64_t *rows = (uint64_t *)(base + o_rows);
+    uint64_t *dst = out_on_device ? mass : (uint64_t *)(base + o_out);
+    double *fsum = (double *)(base + o_fsum);
+    int32_t *flag = (int32_t *)(base + o_flag);
+    hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s->stream, (double *)flag, 1);
+    HIPCHK(hipGetLastError(), where);
+    if (!g.lds) {  // the global-atomic form adds into one zeroed row
+        const int64_t words = nbins;
+        hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s->stream,
+                           (double *)rows, (int)words);
+        HIPCHK(hipGetLastError(), where);
+    }
+    {
+        Launch L(s, QS_KIND_HISTOGRAM, ldexp(1.0, s->n) * (amp_bytes(s->prec) + 4));
+        HIPCHK(launch_histogram(s->prec, s->psi, diag_dev, nbins, g, rows, fsum, flag, dst, s->stream), where);
+        L.done();
+    }
+    std::vector<double> fs((size_t)g.groups);
+    int32_t fl = 0;
+    HIPCHK(hipMemcpyAsync(fs.data(), fsum, fs.size() * 8, hipMemcpyDeviceToHost, s->stream), where);
+    HIPCHK(hipMemcpyAsync(&fl, flag, 4, hipMemcpyDeviceToHost, s->stream), where);
+    if (!out_on_device) HIPCHK(hipMemcpyAsync(mass, dst, (size_t)nbins * 8, hipMemcpyDeviceToHost, s->stream), where);
+    HIPCHK(hipStreamSynchronize(s->stream), where);
+    double total = 0.0;
+    for (double v : fs) total += v;
+    if (fl == 2 || !(total < 3.999))
+        return fail(QS_ERR_STATE, "qs_cost_histogram: state norm too large (|a|^2 sums to 4 or more)");
     return QS_OK;
 }
 

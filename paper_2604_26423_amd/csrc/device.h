@@ -41,6 +41,35 @@ template <> __device__ __forceinline__ double2 expi<double2>(double a)
     return double2{c, s};
 }
 
+// Fixed-point probability mass of one amplitude, shared by the sampler and the
+// cut-value histogram: P = re^2 + im^2 in FP64 with no fused multiply-add and
+// q = floor(P 2^62) as uint64.  *flag becomes 2 when P >= 4 (or NaN): q would
+// not fit in 64 bits.
+__device__ __forceinline__ double prob_fp64(double re, double im)
+{
+    return __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+}
+
+__device__ __forceinline__ uint64_t qmass(double P, int32_t *flag)
+{
+    if (!(P < 4.0)) {
+        *flag = 2;
+        return 0;
+    }
+    return __double2ull_rz(__dmul_rn(P, 4611686018427387904.0));  // 2^62
+}
+
+__device__ __forceinline__ uint64_t qval(double re, double im, int32_t *flag)
+{
+    return qmass(prob_fp64(re, im), flag);
+}
+
+template <typename V>
+__device__ __forceinline__ uint64_t qval_of(const V a, int32_t *flag)
+{
+    return qval((double)a.x, (double)a.y, flag);
+}
+
 // RX(theta) on a pair (a0 = bit clear, a1 = bit set), c = cos(theta/2), s = sin(theta/2):
 //   a0' = c a0 - i s a1,  a1' = -i s a0 + c a1.
 template <typename V, typename R>

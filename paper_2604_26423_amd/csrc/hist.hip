@@ -1,0 +1,146 @@
+// Exact distribution of the cut value under the state (arXiv:2604.26423,
+// Sec. II-D: the noiseless reference distribution that the subsampled means
+// and their 3-sigma thresholds are drawn from).  In the sampler's fixed point,
+//   mass[c] = sum over x with C_t[x] = c of floor((re^2 + im^2) 2^62),
+// with values outside 0..nbins-1 counted in the last bin.  Integer sums make
+// the result independent of the order of accumulation, so it is reproducible
+// bit for bit.
+//
+// One pass over psi and C_t (12 B per c64 amplitude).  Each workgroup owns a
+// contiguous range and keeps a private histogram in LDS (64-bit LDS atomics);
+// at the end it writes that histogram as one row of a scratch matrix, and a
+// second kernel sums the rows per bin.  Histograms wider than the LDS budget
+// add straight into one global row.  The FP64 sum of |a|^2 per workgroup is
+// written beside it so that the host can reject states whose total mass would
+// not fit in 64 bits.
+#include "device.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int kHT = 512;  // threads per workgroup
+
+template <typename V> struct Wide;
+template <> struct Wide<float2> {  // two amplitudes per 16-byte load
+    static constexpr int K = 2;
+    __device__ static void load(const float2 *p, int64_t x, float2 (&a)[2])
+    {
+        const float4 v = *reinterpret_cast<const float4 *>(p + x);
+        a[0] = make_float2(v.x, v.y);
+        a[1] = make_float2(v.z, v.w);
+    }
+    __device__ static void load_c(const int32_t *d, int64_t x, int32_t (&c)[2])
+    {
+        const int2 v = *reinterpret_cast<const int2 *>(d + x);
+        c[0] = v.x;
+        c[1] = v.y;
+    }
+};
+template <> struct Wide<double2> {
+    static constexpr int K = 1;
+    __device__ static void load(const double2 *p, int64_t x, double2 (&a)[1]) { a[0] = p[x]; }
+    __device__ static void load_c(const int32_t *d, int64_t x, int32_t (&c)[1]) { c[0] = d[x]; }
+};
+
+template <typename V, bool LDS>
+__global__ void __launch_bounds__(kHT) hist_kernel(const V *__restrict__ psi, const int32_t *__restrict__ diag,
+                                                   int64_t per, int nbins, uint64_t *rows, double *fsum,
+                                                   int32_t *flag)
+{
+    using Wd = Wide<V>;
+    constexpr int K = Wd::K;
+    extern __shared__ uint64_t bins[];
+    __shared__ double red[kHT / 64];
+    const int tid = threadIdx.x;
+    uint64_t *dst = LDS ? bins : rows;
+    if (LDS) {
+        for (int i = tid; i < nbins; i += kHT) bins[i] = 0;
+        __syncthreads();
+    }
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per;
+    const unsigned last = (unsigned)nbins - 1u;
+    double acc = 0.0;
+    int32_t fl = 0;
+    for (int64_t x = lo + (int64_t)tid * K; x < hi; x += (int64_t)kHT * K) {
+        V a[K];
+        int32_t c[K];
+        Wd::load(psi, x, a);
+        Wd::load_c(diag, x, c);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double P = prob_fp64((double)a[k].x, (double)a[k].y);
+            acc += P;
+            const uint64_t q = qmass(P, &fl);
+            const unsigned b = (unsigned)c[k] > last ? last : (unsigned)c[k];
+            if (q) atomicAdd((unsigned long long *)&dst[b], (unsigned long long)q);
+        }
+    }
+    if (fl) *flag = fl;
+    // fixed-order block sum of the FP64 mass
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kHT / 64; ++w) s += red[w];
+        fsum[blockIdx.x] = s;
+    }
+    if (LDS)
+        for (int i = tid; i < nbins; i += kHT) rows[(int64_t)blockIdx.x * nbins + i] = bins[i];
+}
+
+__global__ void __launch_bounds__(256) hist_rows_kernel(const uint64_t *rows, int nrows, int nbins, uint64_t *out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nbins) return;
+    uint64_t s = 0;
+    for (int r = 0; r < nrows; ++r) s += rows[(int64_t)r * nbins + i];
+    out[i] = s;
+}
+
+}  // namespace
+
+HistGeom hist_geom(int prec, int n, int nbins)
+{
+    HistGeom g{};
+    const int64_t dim = (int64_t)1 << n;
+    const int K = prec == 0 ? 2 : 1;
+    int64_t groups = 1;
+    // about two workgroups per CU, each with at least one full sweep of its threads
+    while (groups < 512 && dim / (groups * 2) >= (int64_t)kHT * K) groups *= 2;
+    g.groups = groups;
+    g.per = dim / groups;
+    g.lds = (int64_t)nbins * 8 <= kHistLdsBytes;
+    g.rows = g.lds ? groups : 1;
+    return g;
+}
+
+hipError_t launch_histogram(int prec, const void *psi, const int32_t *diag, int nbins, const HistGeom &g,
+                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st)
+{
+    const size_t shm = g.lds ? (size_t)nbins * 8 : 0;
+    const dim3 grid((unsigned)g.groups), block(kHT);
+    if (prec == 0) {
+        if (g.lds)
+            hipLaunchKernelGGL((hist_kernel<float2, true>), grid, block, shm, st, (const float2 *)psi, diag, g.per,
+                               nbins, rows, fsum, flag);
+        else
+            hipLaunchKernelGGL((hist_kernel<float2, false>), grid, block, 0, st, (const float2 *)psi, diag, g.per,
+                               nbins, rows, fsum, flag);
+    } else {
+        if (g.lds)
+            hipLaunchKernelGGL((hist_kernel<double2, true>), grid, block, shm, st, (const double2 *)psi, diag, g.per,
+                               nbins, rows, fsum, flag);
+        else
+            hipLaunchKernelGGL((hist_kernel<double2, false>), grid, block, 0, st, (const double2 *)psi, diag, g.per,
+                               nbins, rows, fsum, flag);
+    }
+    if (hipError_t e = hipGetLastError()) return e;
+    hipLaunchKernelGGL(hist_rows_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, st, rows,
+                       (int)g.rows, nbins, out);
+    return hipGetLastError();
+}
+
+}  // namespace qs

@@ -209,4 +209,17 @@ void sample_sizes(int n, int64_t *nsub, int64_t *nblk, int64_t *nchunk);
 hipError_t launch_sample(int prec, const void *psi, int n, const SampleBufs &b, uint64_t seed,
                          int64_t shots, uint64_t *out, hipStream_t st);
 
+// Cut-value histogram.
+constexpr int64_t kHistLdsBytes = 64 << 10;   // private LDS histograms up to 8192 bins
+constexpr int kHistMaxBins = 1 << 24;
+struct HistGeom {
+    int64_t groups;   // workgroups
+    int64_t per;      // amplitudes per workgroup (a power of two)
+    int64_t rows;     // scratch rows of nbins uint64 (groups, or 1 for the global-atomic form)
+    bool lds;         // private histograms in LDS
+};
+HistGeom hist_geom(int prec, int n, int nbins);
+hipError_t launch_histogram(int prec, const void *psi, const int32_t *diag, int nbins, const HistGeom &g,
+                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st);
+
 }  // namespace qs

@@ -22,22 +22,6 @@ constexpr int kChunkBits = 26;   // amplitudes per chunk
 constexpr int kSubPerBlock = 1 << (kBlockBits - kSubBits);            // 128
 constexpr int kBlkPerChunk = 1 << (kChunkBits - kBlockBits);          // 8192
 
-__device__ __forceinline__ uint64_t qval(double re, double im, int32_t *flag)
-{
-    const double P = __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
-    if (!(P < 4.0)) {  // q would not fit in 64 bits (or NaN)
-        *flag = 2;
-        return 0;
-    }
-    return __double2ull_rz(__dmul_rn(P, 4611686018427387904.0));  // 2^62
-}
-
-template <typename V>
-__device__ __forceinline__ uint64_t qval_of(const V a, int32_t *flag)
-{
-    return qval((double)a.x, (double)a.y, flag);
-}
-
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of the output for
 // counter (c0, 0, 0, 0) and key (k0, 0).
 __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t k0)

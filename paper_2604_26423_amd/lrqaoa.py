@@ -128,6 +128,21 @@ class Simulator:
         cuts = self.diag[idx].double().mean().item() / 10.0
         return cuts / (self.cmax / 10.0)
 
+    def cost_histogram(self, on_device: bool = False):
+        """Fixed-point mass of every cut value 0..W_t (tenths); 2^62 = probability 1."""
+        nb = int(self.w_total) + 1
+        if on_device:
+            out = self.torch.empty(nb, dtype=self.torch.int64, device=self.device)
+            return _qs.qs_cost_histogram(self.handle, self.diag, nb, out)
+        return _qs.qs_cost_histogram(self.handle, self.diag, nb)
+
+    def ratio_distribution(self):
+        """(r values, probabilities): the exact distribution of C(x)/C(x*) under
+        the state, from the cut-value histogram."""
+        mass = self.cost_histogram().astype(np.float64)
+        cut = np.arange(len(mass), dtype=np.float64)
+        return cut / self.cmax, mass / mass.sum()
+
     def adjoint(self, theta_zz, theta_x):
         if self.lam is None:
             self.lam = self.torch.empty_like(self.psi)
@@ -157,6 +172,23 @@ class Simulator:
             self.close()
         except Exception:
             pass
+
+
+def mean_of_means(r_values, probs, n_shots: int, sigmas: float = 3.0):
+    """Sec. II-D: the mean approximation ratio over n_shots bitstrings drawn
+    from a distribution of r, summarised by its grand mean and spread.
+
+    From the exact distribution (probs over r_values) the mean of n_shots
+    independent draws has mean mu and standard deviation sigma / sqrt(n_shots);
+    returns (mu, that spread, mu + sigmas * spread), the last being the
+    threshold a measured mean must exceed.
+    """
+    r = np.asarray(r_values, dtype=np.float64)
+    q = np.asarray(probs, dtype=np.float64)
+    q = q / q.sum()
+    mu = float((r * q).sum())
+    sd = float(np.sqrt(max((((r - mu) ** 2) * q).sum(), 0.0)) / np.sqrt(n_shots))
+    return mu, sd, mu + sigmas * sd
 
 
 def _autograd():

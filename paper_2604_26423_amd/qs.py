@@ -22,20 +22,21 @@ QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_HIP, QS_ERR_RANGE, QS_ERR_STATE = range(6)
 QS_C64, QS_C128 = 0, 1
 QS_MAX_QUBITS_C64, QS_MAX_QUBITS_C128 = 34, 33
 (QS_KIND_PASS, QS_KIND_PASS_PHASE, QS_KIND_ADJOINT, QS_KIND_EXPECT, QS_KIND_SAMPLE,
- QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_TURNAROUND, QS_KIND_COUNT) = range(10)
+ QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_TURNAROUND, QS_KIND_HISTOGRAM,
+ QS_KIND_COUNT) = range(11)
 KIND_NAMES = ["pass", "pass_phase", "adjoint", "expect", "sample", "elementwise", "reduce", "small",
-              "turnaround"]
+              "turnaround", "histogram"]
 # kernel symbol behind each kind (kinds that share a kernel are timed together
 # when compared with a profiler's per-kernel statistics)
 KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "adjoint_kernel<reverse>",
                "turnaround": "adjoint_kernel<turnaround>", "expect": "expect_kernel",
                "elementwise": "elementwise", "sample": "sample_kernels", "reduce": "reduce_kernels",
-               "small": "small_kernels"}
+               "small": "small_kernels", "histogram": "hist_kernel"}
 
 # every symbol the public headers declare
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
            "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_apply_cost_layer", "qs_apply_mixer",
-           "qs_forward", "qs_expect", "qs_sample", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
+           "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad", "qs_batch_free"]
 QS_BATCH_MAX_QUBITS = 30
 
@@ -82,6 +83,7 @@ def lib() -> ctypes.CDLL:
         "qs_forward": ([vp, vp, i64, i32, vp, vp, _c_dbl_p, _c_dbl_p], i32),
         "qs_expect": ([vp, vp, _c_dbl_p, _c_dbl_p], i32),
         "qs_sample": ([vp, u64, i64, vp, i32], i32),
+        "qs_cost_histogram": ([vp, vp, i32, vp, i32], i32),
         "qs_adjoint_grad": ([vp, vp, i64, i32, vp, vp, vp, sz, _c_dbl_p, vp, vp], i32),
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
@@ -205,6 +207,17 @@ def qs_sample(s, seed: int, shots: int, out=None) -> np.ndarray:
         return out
     host = np.empty(int(shots), dtype=np.uint64)
     _check(lib().qs_sample(s, int(seed), int(shots), host.ctypes.data if shots > 0 else None, 0))
+    return host
+
+
+def qs_cost_histogram(s, diag_dev, nbins: int, out=None) -> np.ndarray:
+    """Fixed-point mass per cut value (uint64, 2^62 = probability 1), to a new
+    host array or into a device tensor `out` (returned)."""
+    if out is not None:
+        _check(lib().qs_cost_histogram(s, _ptr(diag_dev), int(nbins), _ptr(out), 1))
+        return out
+    host = np.empty(max(int(nbins), 0), dtype=np.uint64)
+    _check(lib().qs_cost_histogram(s, _ptr(diag_dev), int(nbins), host.ctypes.data if nbins > 0 else None, 0))
     return host
 
 

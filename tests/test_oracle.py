@@ -229,6 +229,52 @@ def test_sampling_single_precision_input_is_promoted():
     assert np.array_equal(a, b)
 
 
+# ---------------------------------------------------------------- cut-value histogram
+def test_histogram_uniform_state_counts_the_diagonal():
+    """On |+>^n every q(x) is 2^(62-n) exactly, so the histogram is the count
+    of basis states per cut value times that mass."""
+    n = 11
+    w = inst(n, 2)
+    diag = oracle.cost_diagonal(n, w)
+    W = oracle.weight_total(w)
+    psi = np.full(1 << n, 2 ** (-n / 2), dtype=np.complex128)
+    got = oracle.cost_histogram(psi, diag, W + 1)
+    want = np.bincount(diag, minlength=W + 1).astype(np.uint64) * np.uint64(1 << (62 - n))
+    assert np.array_equal(got, want)
+
+
+def test_histogram_delta_state_and_overflow_bin():
+    n = 9
+    w = inst(n, 3)
+    diag = oracle.cost_diagonal(n, w)
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    x0 = 300
+    psi[x0] = -1j
+    W = oracle.weight_total(w)
+    h = oracle.cost_histogram(psi, diag, W + 1)
+    assert h[diag[x0]] == 1 << 62 and int(h.sum()) == 1 << 62
+    # values at or above nbins land in the last bin
+    nb = int(diag[x0])
+    h2 = oracle.cost_histogram(psi, diag, nb)
+    assert h2[-1] == 1 << 62 and int(h2.sum()) == 1 << 62
+
+
+def test_histogram_moments_match_the_state():
+    """Total mass = 2^62 norm and mean cut = <C>, up to the floor of each q."""
+    n = 10
+    w = inst(n, 5)
+    diag = oracle.cost_diagonal(n, w)
+    psi = oracle.simulate(n, w, *oracle.gate_angles(*oracle.ramp_midpoint(3, 0.7, 0.5)))
+    h = oracle.cost_histogram(psi, diag, oracle.weight_total(w) + 1).astype(np.float64)
+    e, nrm = oracle.expect(psi, diag)
+    total = h.sum() / 2.0 ** 62
+    assert abs(total - nrm) <= (1 << n) * 2.0 ** -62 + 1e-15
+    mean = (np.arange(len(h)) * h).sum() / h.sum() / 10
+    assert abs(mean - e) <= 1e-12 * e
+    # the distribution differs from the uniform one (the circuit moves mass up)
+    assert mean > oracle.weight_total(w) / 20
+
+
 # ---------------------------------------------------------------- gradient
 @pytest.mark.parametrize("convention", ["paper", "literal"])
 def test_adjoint_vs_finite_differences(convention):

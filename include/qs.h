@@ -55,6 +55,26 @@ typedef enum { QS_C64 = 0, QS_C128 = 1 } qs_prec;
 #define QS_MAX_QUBITS_C64 34
 #define QS_MAX_QUBITS_C128 33
 
+/*
+ * Complement-symmetric layout, OR'ed into the precision argument of
+ * qs_state_bytes and qs_alloc (e.g. QS_C64 | QS_SYM).
+ *
+ * Every state the circuit produces from |+>^n satisfies psi(x) = psi(~x),
+ * ~x the complement of all n bits, because the cut value of eq. (6), |+>^n
+ * and the mixer of eq. (3) are all invariant under flipping every qubit.  The
+ * layout stores only the 2^(n-1) amplitudes with bit n-1 clear, at index z:
+ *   y = x mod 2^(n-1),  z_q = y_q XOR y_(q+1) (q < n-2),  z_(n-2) = y_(n-2);
+ * conversely y_q = z_q XOR z_(q+1) XOR ... XOR z_(n-2), and psi(x) is the
+ * stored value at z(y) for x = y and for x = ~y.  Memory and traffic are
+ * halved, so one more qubit fits (n <= 35 complex64, 34 complex128); the
+ * layout needs n >= 15 (complex64) or n >= 14 (complex128).
+ * A symmetric state uses a diagonal from qs_cost_diagonal_sym (same z order).
+ * Results refer to the full state: qs_expect and qs_forward report the full
+ * norm, qs_cost_histogram the full masses, qs_sample full indices x (rule in
+ * qs_sample).  qs_state_ptr returns the stored half.
+ */
+#define QS_SYM 16
+
 typedef struct qs_state_s *qs_state;
 
 /* Message for the calling thread's last failed call ("" if none). */
@@ -106,6 +126,14 @@ qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev,
                            int64_t *w_total_tenths, int32_t *cmax_tenths, void *hip_stream);
 
 /*
+ * Cost diagonal for the complement-symmetric layout: 2^(n-1) int32 in z order
+ * (see QS_SYM), entry z = C_t[x] for x = y(z) with bit n-1 clear.  Same
+ * arguments, outputs and errors as qs_cost_diagonal, for 14 <= n <= 35.
+ */
+qs_status qs_cost_diagonal_sym(int n, const int32_t *w_tenths, int32_t *diag_dev,
+                               int64_t *w_total_tenths, int32_t *cmax_tenths, void *hip_stream);
+
+/*
  * One cost layer, eq. (2): prod_{i<j} RZZ(theta_zz * w_ij), applied as the
  * diagonal phase exp(-i theta_zz (W_t - 2 C_t[x]) / 20) on every amplitude.
  * The phase argument is reduced modulo 2 pi in FP64.
@@ -142,6 +170,9 @@ qs_status qs_expect(qs_state s, const int32_t *diag_dev, double *exp_c, double *
  *   (s, 0, 0, 0) and key (seed, 0), u = floor(r T / 2^64), and returns
  *   x_s = min { x : F(x) > u }.
  * out: shots uint64 values, on the device if out_on_device, else on the host.
+ * Complement-symmetric states (QS_SYM) apply the rule to the stored half in
+ * z order, which draws z, and return x = y(z) if bit 63 of word 1 of the same
+ * Philox output is clear, else its complement ~y(z) over n bits.
  * Errors: QS_ERR_ARG (shots < 0, null out), QS_ERR_STATE (T = 0 or the
  * state norm is 4 or more, where q would overflow).
  */

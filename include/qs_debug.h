@@ -23,8 +23,14 @@ extern "C" {
  *   - the fused kernel sequence applies, for every layer k, the cost phase once
  *     after all of layer k-1's mixer and before any of layer k's, and every
  *     pass's mixer once per layer.
+ * With prec | QS_SYM (16) the complement-symmetric plan is checked instead:
+ * each of the n mixer factors in z coordinates (z_0; z_(j-1) z_j for
+ * j = 1..n-2; z_(n-2)) is applied by exactly one pass, on adjacent bits, and
+ * every window sequence covers them; tile maps are checked over the 2^(n-1)
+ * stored indices.
  * Returns 0 when every check holds, else 1 with a description in msg
- * (msg may be NULL).  n outside 1..34 or prec not 0/1 returns 2.
+ * (msg may be NULL).  n outside 1..34 (15..35 or 14..34 with QS_SYM), or
+ * prec not 0/1, returns 2.
  */
 int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len);
 

@@ -55,6 +55,10 @@ def lib():
         L.oracle_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
         L.oracle_philox4x64_10.restype = None
         L.oracle_sample.argtypes = [ctypes.c_int, _f64p, ctypes.c_uint64, ctypes.c_int64, _u64p]
+        L.oracle_sym_y_of_z.argtypes = [ctypes.c_int, ctypes.c_uint64]
+        L.oracle_sym_y_of_z.restype = ctypes.c_uint64
+        L.oracle_sym_half.argtypes = [ctypes.c_int, _f64p, _f64p]
+        L.oracle_sample_sym.argtypes = [ctypes.c_int, _f64p, ctypes.c_uint64, ctypes.c_int64, _u64p]
         L.oracle_cost_histogram.argtypes = [ctypes.c_int, _f64p, _i32p, ctypes.c_int64, _u64p]
         L.oracle_adjoint.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p,
                                      ctypes.POINTER(ctypes.c_double), _f64p, _f64p]
@@ -158,6 +162,28 @@ def sample(psi, seed: int, shots: int) -> np.ndarray:
     n = int(psi.size).bit_length() - 1
     out = np.empty(shots, dtype=np.uint64)
     _check(lib().oracle_sample(n, psi.view(np.float64), int(seed), int(shots), out), "sample")
+    return out
+
+
+def sym_y_of_z(n: int, z: int) -> int:
+    """Basis state (bit n-1 clear) of complement-symmetric index z."""
+    return int(lib().oracle_sym_y_of_z(n, int(z)))
+
+
+def sym_half(psi) -> np.ndarray:
+    """Stored half (z order) of a complement-symmetric full state."""
+    p = _as_c128(psi)
+    n = int(p.size).bit_length() - 1
+    out = np.empty(p.size // 2, dtype=np.complex128)
+    _check(lib().oracle_sym_half(n, p.view(np.float64), out.view(np.float64)), "sym_half")
+    return out
+
+
+def sample_sym(half, n: int, seed: int, shots: int) -> np.ndarray:
+    """Shots of n-qubit basis states from a complement-symmetric half state."""
+    h = _as_c128(half)
+    out = np.empty(shots, dtype=np.uint64)
+    _check(lib().oracle_sample_sym(n, h.view(np.float64), int(seed), int(shots), out), "sample_sym")
     return out
 
 

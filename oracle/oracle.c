@@ -383,6 +383,77 @@ int oracle_sample(int n, const double *psi, uint64_t seed, int64_t shots, uint64
 }
 
 /*
+ * Complement-symmetric storage.  psi(x) = psi(~x) for every state of the
+ * circuit (C(x) = C(~x) for the cut of eq. 6; |+> and the mixer of eq. 3 are
+ * invariant under flipping all qubits), so a state is fixed by the half with
+ * bit n-1 clear.  That half is indexed by z with y = x mod 2^(n-1):
+ *   y_q = z_q XOR z_(q+1) XOR ... XOR z_(n-2),
+ * computed here bit by bit from the top.
+ */
+uint64_t oracle_sym_y_of_z(int n, uint64_t z)
+{
+    uint64_t y = 0, acc = 0;
+    for (int q = n - 2; q >= 0; q--) {
+        acc ^= (z >> q) & 1u;
+        y |= acc << q;
+    }
+    return y;
+}
+
+/* The stored half of a full state: half[z] = psi[y(z)] (interleaved re, im). */
+int oracle_sym_half(int n, const double *psi, double *half)
+{
+    if (n < 2 || !psi || !half) return 1;
+    const int64_t h = (int64_t)1 << (n - 1);
+    for (int64_t z = 0; z < h; z++) {
+        const uint64_t y = oracle_sym_y_of_z(n, (uint64_t)z);
+        half[2 * z] = psi[2 * y];
+        half[2 * z + 1] = psi[2 * y + 1];
+    }
+    return 0;
+}
+
+/*
+ * Shots from a complement-symmetric half state (z order): the rule of
+ * oracle_sample applied to the half draws z with probability |half[z]|^2 / sum;
+ * the shot is y(z) when bit 63 of word 1 of the same Philox output is clear,
+ * else the complement of y(z) over n bits -- each of x, ~x with half the
+ * mass, as in the full state.
+ */
+int oracle_sample_sym(int n, const double *half, uint64_t seed, int64_t shots, uint64_t *out)
+{
+    const int64_t dim = (int64_t)1 << (n - 1);
+    uint64_t *F = (uint64_t *)malloc((size_t)dim * sizeof(uint64_t));
+    if (!F) return 2;
+    uint64_t acc = 0;
+    for (int64_t z = 0; z < dim; z++) {
+        double re = half[2 * z], im = half[2 * z + 1];
+        double P = re * re + im * im;
+        acc += (uint64_t)(P * 4611686018427387904.0); /* 2^62 */
+        F[z] = acc;
+    }
+    const uint64_t T = acc;
+    if (T == 0) { free(F); return 3; }
+    const uint64_t full = (n == 64) ? ~(uint64_t)0 : (((uint64_t)1 << n) - 1);
+    for (int64_t s = 0; s < shots; s++) {
+        uint64_t ctr[4] = {(uint64_t)s, 0, 0, 0}, key[2] = {seed, 0}, r[4];
+        oracle_philox4x64_10(ctr, key, r);
+        uint64_t hi, lo;
+        mul128(r[0], T, &hi, &lo);
+        int64_t a = 0, b = dim - 1;
+        while (a < b) {
+            int64_t mid = a + (b - a) / 2;
+            if (F[mid] > hi) b = mid; else a = mid + 1;
+        }
+        uint64_t x = oracle_sym_y_of_z(n, (uint64_t)a);
+        if (r[1] >> 63) x ^= full;
+        out[s] = x;
+    }
+    free(F);
+    return 0;
+}
+
+/*
  * Exact distribution of the cut value under the state: the noiseless
  * reference distribution of Sec. II-D without subsampling noise.  In the
  * sampler's fixed point,

@@ -47,6 +47,18 @@ qs_status hip_fail(hipError_t e, const char *where)
     } while (0)
 
 int max_qubits(int prec) { return prec == QS_C64 ? QS_MAX_QUBITS_C64 : QS_MAX_QUBITS_C128; }
+
+// Split a precision argument into the precision and the QS_SYM flag; false if invalid.
+bool parse_prec(int arg, int *prec, int *sym)
+{
+    *sym = (arg & QS_SYM) ? 1 : 0;
+    *prec = arg & ~QS_SYM;
+    return *prec == QS_C64 || *prec == QS_C128;
+}
+
+// Qubit range of a layout: the symmetric one needs more than a tile of stored bits.
+int min_qubits(int prec, int sym) { return sym ? (prec == QS_C64 ? kTileBitsC64 : kTileBitsC128) + 2 : 1; }
+int max_qubits(int prec, int sym) { return sym ? max_qubits(prec) + 1 : max_qubits(prec); }
 size_t amp_bytes(int prec) { return prec == QS_C64 ? 8 : 16; }
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
@@ -81,7 +93,8 @@ struct DevBuf {
 }  // namespace
 
 struct qs_state_s {
-    int n = 0, prec = 0;
+    int n = 0, prec = 0;  // n: stored index bits (qubits, or qubits - 1 when sym)
+    int nq = 0, sym = 0;  // qubits; complement-symmetric layout
     void *psi = nullptr;
     bool own = false;
     hipStream_t stream = nullptr;
@@ -165,7 +178,7 @@ RxStage rx_stage(double theta, int m, double *factor)
 }
 
 PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassGeom &g, const KSpec &k,
-                       const Circuit &cc, int tb)
+                       const Circuit &cc, int tb, int sym = 0)
 {
     const int T = tile_bits(prec);
     PassProg pp{};
@@ -178,7 +191,8 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     pp.c = g.c;
     pp.q0 = g.q0;
     pp.targets = g.targets;
-    pp.ntargets = __builtin_popcount(g.targets);
+    pp.pairs = g.pairs;
+    pp.ntargets = __builtin_popcount(g.targets) + __builtin_popcount(g.pairs);
     pp.width = T - g.c;
     pp.init = k.init;
     pp.has_pre = k.pre >= 0;
@@ -188,11 +202,11 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     pp.load_win = tb;
     pp.fpre = pp.fpost = 1.0;
     if (pp.has_pre) {
-        pp.A = plan_windows(tb, g.targets, T, tb);
-        pp.B = plan_windows(pp.A.s[pp.A.cnt - 1], g.targets, T, tb);
+        pp.A = plan_windows(tb, g.targets, g.pairs, T, tb);
+        pp.B = plan_windows(pp.A.s[pp.A.cnt - 1], g.targets, g.pairs, T, tb);
         pp.pre = rx_stage(cc.tx[k.pre], pp.ntargets, &pp.fpre);
     } else {
-        pp.B = plan_windows(tb, g.targets, T, tb);
+        pp.B = plan_windows(tb, g.targets, g.pairs, T, tb);
     }
     if (pp.has_post) pp.post = rx_stage(cc.tx[k.post], pp.ntargets, &pp.fpost);
     pp.factor = pp.fpre * pp.fpost;
@@ -201,13 +215,19 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     if (pp.has_phase) pp.theta_zz = cc.tzz[k.phase];
     pp.W = cc.W;
     pp.phase_levels = phase_table_levels(cc.W);
-    pp.amp0 = sqrt(ldexp(1.0, -n));
+    pp.amp0 = sqrt(ldexp(1.0, -(n + sym)));
     return pp;
 }
 
 PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb)
 {
-    return make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb);
+    return make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb, s->sym);
+}
+
+// Pass plan of a state's layout.
+std::vector<PassGeom> plan_for(qs_state s)
+{
+    return s->sym ? plan_passes_sym(s->nq, s->prec) : plan_passes(s->n, s->prec);
 }
 
 // Launch one tile kernel over a persistent grid; returns the grid (the number
@@ -339,7 +359,7 @@ qs_status run_forward(qs_state s, const Circuit &cc, bool readout, const char *w
     HIPCHK(s->results.ensure(64 * sizeof(double)), where);
     if (cc.p == 0) {
         Launch L(s, QS_KIND_ELEMENTWISE, ldexp(1.0, s->n) * amp_bytes(s->prec));
-        HIPCHK(launch_init_plus(s->prec, s->psi, s->n, s->stream), where);
+        HIPCHK(launch_init_plus(s->prec, s->psi, s->n, s->nq, s->stream), where);
         L.done();
         if (readout) {
             int64_t nb = 0;
@@ -354,7 +374,7 @@ qs_status run_forward(qs_state s, const Circuit &cc, bool readout, const char *w
     }
     if (s->n <= T) return run_small_forward(s, cc, readout, where);
 
-    const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
+    const std::vector<PassGeom> geo = plan_for(s);
     std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     if (readout) ks.back().readout = 1;
     HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
@@ -413,7 +433,7 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     HIPCHK(zero_results(s, nres), where);
     if (s->n <= T) return run_small_adjoint(s, cc, lam, where);
 
-    const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
+    const std::vector<PassGeom> geo = plan_for(s);
     const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     const int64_t ntiles = (int64_t)1 << (s->n - T);
     HIPCHK(ensure_partials(s, std::max(pass_grid(s->prec, 0, ntiles), pass_grid(s->prec, 1, ntiles))), where);
@@ -494,13 +514,13 @@ DiagScratch diag_scratch_layout(int nmax, int nres)
 // Queue the diagonal of one circuit; its C_max lands in result slot `res`.
 // `wm` must stay alive until the stream has run the copy.
 hipError_t build_diagonal(int n, const std::vector<int32_t> &wm, int32_t *diag, char *scratch, const DiagScratch &L,
-                          int res, hipStream_t st)
+                          int res, hipStream_t st, int sym = 0)
 {
     hipError_t e = hipMemcpyAsync(scratch, wm.data(), (size_t)n * n * 4, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     return launch_cost_diagonal(n, (const int32_t *)scratch, diag, (int32_t *)(scratch + L.off_low),
                                 (int32_t *)(scratch + L.off_wg), (int32_t *)(scratch + L.off_tmp),
-                                (int32_t *)(scratch + L.off_res) + res, st);
+                                (int32_t *)(scratch + L.off_res) + res, st, sym);
 }
 
 }  // namespace
@@ -512,28 +532,33 @@ const char *qs_last_error(void) { return g_err.c_str(); }
 
 const char *qs_version(void) { return "libqs 0.1 (gfx950)"; }
 
-size_t qs_state_bytes(int n, int prec)
+size_t qs_state_bytes(int n, int prec_arg)
 {
-    if (prec != QS_C64 && prec != QS_C128) return 0;
-    if (n < 1 || n > max_qubits(prec)) return 0;
-    return ((size_t)1 << n) * amp_bytes(prec);
+    int prec, sym;
+    if (!parse_prec(prec_arg, &prec, &sym)) return 0;
+    if (n < min_qubits(prec, sym) || n > max_qubits(prec, sym)) return 0;
+    return ((size_t)1 << (n - sym)) * amp_bytes(prec);
 }
 
-qs_status qs_alloc(int n, int prec, void *dev_buf, size_t buf_bytes, void *hip_stream, qs_state *out)
+qs_status qs_alloc(int n, int prec_arg, void *dev_buf, size_t buf_bytes, void *hip_stream, qs_state *out)
 {
     try {
         if (!out) return fail(QS_ERR_ARG, "null output handle pointer");
         *out = nullptr;
-        if (prec != QS_C64 && prec != QS_C128) return fail(QS_ERR_ARG, "bad precision %d", prec);
-        if (n < 1 || n > max_qubits(prec))
-            return fail(QS_ERR_ARG, "n = %d outside 1..%d for this precision", n, max_qubits(prec));
-        const size_t need = qs_state_bytes(n, prec);
+        int prec, sym;
+        if (!parse_prec(prec_arg, &prec, &sym)) return fail(QS_ERR_ARG, "bad precision %d", prec_arg);
+        if (n < min_qubits(prec, sym) || n > max_qubits(prec, sym))
+            return fail(QS_ERR_ARG, "n = %d outside %d..%d for this precision and layout", n, min_qubits(prec, sym),
+                        max_qubits(prec, sym));
+        const size_t need = qs_state_bytes(n, prec_arg);
         if (dev_buf) {
             if (buf_bytes < need) return fail(QS_ERR_ARG, "buffer too small: %zu < %zu bytes", buf_bytes, need);
             if (!aligned(dev_buf, 256)) return fail(QS_ERR_ARG, "state buffer must be 256-byte aligned");
         }
         qs_state s = new qs_state_s();
-        s->n = n;
+        s->n = n - sym;
+        s->nq = n;
+        s->sym = sym;
         s->prec = prec;
         s->stream = (hipStream_t)hip_stream;
         if (dev_buf) {
@@ -589,16 +614,16 @@ qs_status qs_init_plus(qs_state s)
 {
     if (qs_status st = check_state(s)) return st;
     Launch L(s, QS_KIND_ELEMENTWISE, ldexp(1.0, s->n) * amp_bytes(s->prec));
-    HIPCHK(launch_init_plus(s->prec, s->psi, s->n, s->stream), "qs_init_plus");
+    HIPCHK(launch_init_plus(s->prec, s->psi, s->n, s->nq, s->stream), "qs_init_plus");
     L.done();
     return QS_OK;
 }
 
-qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
-                           int32_t *cmax_tenths, void *hip_stream)
+namespace {
+qs_status cost_diagonal_impl(int n, int sym, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
+                             int32_t *cmax_tenths, void *hip_stream)
 {
     try {
-        if (n < 1 || n > QS_MAX_QUBITS_C64) return fail(QS_ERR_ARG, "n = %d outside 1..%d", n, QS_MAX_QUBITS_C64);
         if (!diag_dev) return fail(QS_ERR_ARG, "null diagonal buffer");
         if (!aligned(diag_dev, 16)) return fail(QS_ERR_ARG, "diagonal buffer must be 16-byte aligned");
         std::vector<int32_t> wm;
@@ -608,7 +633,7 @@ qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev, in
         const DiagScratch L = diag_scratch_layout(n, 1);
         char *scratch = nullptr;
         HIPCHK(hipMalloc(&scratch, L.total), "qs_cost_diagonal");
-        hipError_t he = build_diagonal(n, wm, diag_dev, scratch, L, 0, st);
+        hipError_t he = build_diagonal(n, wm, diag_dev, scratch, L, 0, st, sym);
         int32_t cmax = 0;
         if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch + L.off_res, 4, hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
@@ -620,6 +645,22 @@ qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev, in
     } catch (...) {
         return fail(QS_ERR_OOM, "qs_cost_diagonal: host allocation failed");
     }
+}
+}  // namespace
+
+qs_status qs_cost_diagonal(int n, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
+                           int32_t *cmax_tenths, void *hip_stream)
+{
+    if (n < 1 || n > QS_MAX_QUBITS_C64) return fail(QS_ERR_ARG, "n = %d outside 1..%d", n, QS_MAX_QUBITS_C64);
+    return cost_diagonal_impl(n, 0, w_tenths, diag_dev, w_total_tenths, cmax_tenths, hip_stream);
+}
+
+qs_status qs_cost_diagonal_sym(int n, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
+                               int32_t *cmax_tenths, void *hip_stream)
+{
+    if (n < 14 || n > QS_MAX_QUBITS_C64 + 1)
+        return fail(QS_ERR_ARG, "n = %d outside 14..%d", n, QS_MAX_QUBITS_C64 + 1);
+    return cost_diagonal_impl(n, 1, w_tenths, diag_dev, w_total_tenths, cmax_tenths, hip_stream);
 }
 
 qs_status qs_apply_cost_layer(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, double theta_zz)
@@ -654,7 +695,7 @@ qs_status qs_apply_mixer(qs_state s, double theta_x)
         L.done();
         return QS_OK;
     }
-    const std::vector<PassGeom> geo = plan_passes(s->n, s->prec);
+    const std::vector<PassGeom> geo = plan_for(s);
     HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
     const double tx[1] = {theta_x}, tzz[1] = {0.0};
     Circuit cc{nullptr, 0, 1, tzz, tx};
@@ -681,7 +722,7 @@ qs_status qs_forward(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths
             double r[2];
             if (qs_status st = read_results(s, r, 2, "qs_forward")) return st;
             *exp_c = (r[1] / 10.0) / r[0];
-            if (norm) *norm = r[0];
+            if (norm) *norm = r[0] * (s->sym ? 2.0 : 1.0);
         }
         return QS_OK;
     } catch (...) {
@@ -706,7 +747,7 @@ qs_status qs_expect(qs_state s, const int32_t *diag_dev, double *exp_c, double *
     double r[2];
     if (qs_status st = read_results(s, r, 2, where)) return st;
     *exp_c = (r[1] / 10.0) / r[0];
-    if (norm) *norm = r[0];
+    if (norm) *norm = r[0] * (s->sym ? 2.0 : 1.0);
     return QS_OK;
 }
 
@@ -738,7 +779,7 @@ qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int
     HIPCHK(hipGetLastError(), where);
     {
         Launch L(s, QS_KIND_SAMPLE, ldexp(1.0, s->n) * amp_bytes(s->prec) + (double)shots * 8);
-        HIPCHK(launch_sample(s->prec, s->psi, s->n, b, seed, shots, dst, s->stream), where);
+        HIPCHK(launch_sample(s->prec, s->psi, s->n, b, seed, shots, dst, s->stream, s->sym ? s->nq : 0), where);
         L.done();
     }
     int32_t flag = 0;
@@ -781,7 +822,7 @@ qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, 
     }
     {
         Launch L(s, QS_KIND_HISTOGRAM, ldexp(1.0, s->n) * (amp_bytes(s->prec) + 4));
-        HIPCHK(launch_histogram(s->prec, s->psi, diag_dev, nbins, g, rows, fsum, flag, dst, s->stream), where);
+        HIPCHK(launch_histogram(s->prec, s->psi, diag_dev, nbins, g, rows, fsum, flag, dst, s->stream, s->sym), where);
         L.done();
     }
     std::vector<double> fs((size_t)g.groups);
@@ -792,6 +833,7 @@ qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, 
     HIPCHK(hipStreamSynchronize(s->stream), where);
     double total = 0.0;
     for (double v : fs) total += v;
+    if (s->sym) total *= 2.0;
     if (fl == 2 || !(total < 3.999))
         return fail(QS_ERR_STATE, "qs_cost_histogram: state norm too large (|a|^2 sums to 4 or more)");
     return QS_OK;

@@ -131,13 +131,59 @@ __device__ __forceinline__ void rxt_reg_mask(V (&v)[NR], uint32_t mask, R u)
     if constexpr (NR >= 64) { if (mask & 32u) rxt_reg_bit<5>(v, u); }
 }
 
-// RX of a stage on the register bits in mask; sign = -1 applies RX(-theta).
+// Two-bit factors exp(-i theta/2 X_a X_b) on register bits K and K+1 (the
+// mixer in complement-symmetric coordinates, see plan.h): the amplitudes at r
+// and r ^ (3 << K) form the pair, with the same 2x2 update as RX.
+template <int K, typename V, int NR, typename R>
+__device__ __forceinline__ void rx_reg_bit2(V (&v)[NR], R c, R s)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) rx_pair(v[r], v[r ^ (3 << K)], c, s);
+}
+
+template <int K, typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_bit2(V (&v)[NR], R u)
+{
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) rxt_pair(v[r], v[r ^ (3 << K)], u);
+}
+
+// Bit K of pmask selects the factor on register bits K and K+1.
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rx_reg_pairs(V (&v)[NR], uint32_t pmask, R c, R s)
+{
+    if constexpr (NR > 2) { if (pmask & 1u) rx_reg_bit2<0>(v, c, s); }
+    if constexpr (NR > 4) { if (pmask & 2u) rx_reg_bit2<1>(v, c, s); }
+    if constexpr (NR > 8) { if (pmask & 4u) rx_reg_bit2<2>(v, c, s); }
+    if constexpr (NR >= 32) { if (pmask & 8u) rx_reg_bit2<3>(v, c, s); }
+    if constexpr (NR >= 64) { if (pmask & 16u) rx_reg_bit2<4>(v, c, s); }
+}
+
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_pairs(V (&v)[NR], uint32_t pmask, R u)
+{
+    if constexpr (NR > 2) { if (pmask & 1u) rxt_reg_bit2<0>(v, u); }
+    if constexpr (NR > 4) { if (pmask & 2u) rxt_reg_bit2<1>(v, u); }
+    if constexpr (NR > 8) { if (pmask & 4u) rxt_reg_bit2<2>(v, u); }
+    if constexpr (NR >= 32) { if (pmask & 8u) rxt_reg_bit2<3>(v, u); }
+    if constexpr (NR >= 64) { if (pmask & 16u) rxt_reg_bit2<4>(v, u); }
+}
+
+// RX of a stage on the register bits in mask (and the two-bit factors in
+// pmask); sign = -1 applies RX(-theta).
 template <typename V, int NR>
-__device__ __forceinline__ void stage_rx(V (&v)[NR], uint32_t mask, const RxStage &st, int sign)
+__device__ __forceinline__ void stage_rx(V (&v)[NR], uint32_t mask, uint32_t pmask, const RxStage &st, int sign)
 {
     using R = typename Real<V>::T;
-    if (st.tan) rxt_reg_mask(v, mask, (R)(sign * st.u));
-    else rx_reg_mask(v, mask, (R)st.c, (R)(sign * st.s));
+    if (st.tan) {
+        rxt_reg_mask(v, mask, (R)(sign * st.u));
+        if (pmask) rxt_reg_pairs(v, pmask, (R)(sign * st.u));
+    } else {
+        rx_reg_mask(v, mask, (R)st.c, (R)(sign * st.s));
+        if (pmask) rx_reg_pairs(v, pmask, (R)st.c, (R)(sign * st.s));
+    }
 }
 
 // Im <lam| X_q |psi> restricted to the pairs held in registers, for register bit K:
@@ -168,6 +214,34 @@ __device__ __forceinline__ double imx_reg_mask(const V (&l)[NR], const V (&p)[NR
     if constexpr (NR > 8) { if (mask & 8u) acc += imx_reg_bit<3>(l, p); }
     if constexpr (NR >= 32) { if (mask & 16u) acc += imx_reg_bit<4>(l, p); }
     if constexpr (NR >= 64) { if (mask & 32u) acc += imx_reg_bit<5>(l, p); }
+    return acc;
+}
+
+// Im <lam| X_a X_b |psi> for the two-bit factor on register bits K, K+1.
+template <int K, typename V, int NR>
+__device__ __forceinline__ double imx_reg_bit2(const V (&l)[NR], const V (&p)[NR])
+{
+    using R = typename Real<V>::T;
+    R acc = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        if (!(r & (1 << K))) {
+            const int q = r ^ (3 << K);
+            const V l0 = l[r], l1 = l[q], p0 = p[r], p1 = p[q];
+            acc += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
+        }
+    return (double)acc;
+}
+
+template <typename V, int NR>
+__device__ __forceinline__ double imx_reg_pairs(const V (&l)[NR], const V (&p)[NR], uint32_t pmask)
+{
+    double acc = 0.0;
+    if constexpr (NR > 2) { if (pmask & 1u) acc += imx_reg_bit2<0>(l, p); }
+    if constexpr (NR > 4) { if (pmask & 2u) acc += imx_reg_bit2<1>(l, p); }
+    if constexpr (NR > 8) { if (pmask & 4u) acc += imx_reg_bit2<2>(l, p); }
+    if constexpr (NR >= 32) { if (pmask & 8u) acc += imx_reg_bit2<3>(l, p); }
+    if constexpr (NR >= 64) { if (pmask & 16u) acc += imx_reg_bit2<4>(l, p); }
     return acc;
 }
 

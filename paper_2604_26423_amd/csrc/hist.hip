@@ -91,13 +91,14 @@ __global__ void __launch_bounds__(kHT) hist_kernel(const V *__restrict__ psi, co
         for (int i = tid; i < nbins; i += kHT) rows[(int64_t)blockIdx.x * nbins + i] = bins[i];
 }
 
-__global__ void __launch_bounds__(256) hist_rows_kernel(const uint64_t *rows, int nrows, int nbins, uint64_t *out)
+__global__ void __launch_bounds__(256) hist_rows_kernel(const uint64_t *rows, int nrows, int nbins, int shift,
+                                                        uint64_t *out)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nbins) return;
     uint64_t s = 0;
     for (int r = 0; r < nrows; ++r) s += rows[(int64_t)r * nbins + i];
-    out[i] = s;
+    out[i] = s << shift;
 }
 
 }  // namespace
@@ -118,7 +119,7 @@ HistGeom hist_geom(int prec, int n, int nbins)
 }
 
 hipError_t launch_histogram(int prec, const void *psi, const int32_t *diag, int nbins, const HistGeom &g,
-                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st)
+                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st, int shift)
 {
     const size_t shm = g.lds ? (size_t)nbins * 8 : 0;
     const dim3 grid((unsigned)g.groups), block(kHT);
@@ -139,7 +140,7 @@ hipError_t launch_histogram(int prec, const void *psi, const int32_t *diag, int 
     }
     if (hipError_t e = hipGetLastError()) return e;
     hipLaunchKernelGGL(hist_rows_kernel, dim3((unsigned)((nbins + 255) / 256)), dim3(256), 0, st, rows,
-                       (int)g.rows, nbins, out);
+                       (int)g.rows, nbins, shift, out);
     return hipGetLastError();
 }
 

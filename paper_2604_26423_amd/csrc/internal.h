@@ -15,7 +15,7 @@ constexpr int kFwdThreadBits = QS_FWD_TB; // forward tile kernels: 256 threads
 constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
-constexpr int kMaxWindows = 4;        // register windows per butterfly stage
+constexpr int kMaxWindows = 8;        // register windows per butterfly stage
 constexpr int kSmallMaxLayers = 32;   // layers per launch of the single-workgroup kernel
 constexpr int kSlots = 4;             // FP64 partial sums per workgroup
 
@@ -51,8 +51,9 @@ struct PassProg {
     double *partials;     // kSlots doubles per workgroup
     int64_t ntiles;       // 2^(n - T); workgroups loop over tiles
     int n, c, q0;
-    uint32_t targets;     // mask of tile bits that are gate targets: [c, T)
-    int ntargets;         // popcount(targets)
+    uint32_t targets;     // mask of tile bits that are single-qubit gate targets
+    uint32_t pairs;       // bit e: two-bit factor on tile bits e, e+1 (complement-symmetric storage)
+    int ntargets;         // factors per stage: popcount(targets) + popcount(pairs)
     int width;            // strided tile bits T - c
     int xcd_remap;        // map consecutive tiles to one XCD
     int init;             // start from |+>^n instead of loading
@@ -182,7 +183,9 @@ hipError_t launch_small_forward(int prec, const SmallProg &sp, hipStream_t st);
 hipError_t launch_small_adjoint(int prec, const SmallProg &sp, hipStream_t st);
 
 // Elementwise and readout kernels.
-hipError_t launch_init_plus(int prec, void *psi, int n, hipStream_t st);
+// |+>: 2^n stored amplitudes, each 2^(-nq/2) (nq = n, or n + 1 in the
+// complement-symmetric layout).
+hipError_t launch_init_plus(int prec, void *psi, int n, int nq, hipStream_t st);
 hipError_t launch_cost_layer(int prec, void *psi, const int32_t *diag, int n, int64_t W,
                              double theta, hipStream_t st);
 hipError_t launch_expect(int prec, const void *psi, const int32_t *diag, int n,
@@ -193,10 +196,12 @@ hipError_t launch_reduce(const double *partials, int64_t count, double *tmp, dou
 int64_t reduce_tmp_doubles(int64_t count);
 
 // Cost diagonal.
+// sym = 1: the 2^(n-1) entries of the complement-symmetric layout (plan.h)
+// in z order; n is the qubit count of the graph.
 hipError_t launch_cost_diagonal(int n, const int32_t *wmat_dev, int32_t *diag, int32_t *low_table,
                                 int32_t *wg_max, int32_t *tmp_max, int32_t *cmax_dev,
-                                hipStream_t st);
-int64_t diag_wg_count(int n);
+                                hipStream_t st, int sym = 0);
+int64_t diag_wg_count(int n, int sym = 0);
 
 // Sampling.
 struct SampleBufs {
@@ -206,8 +211,11 @@ struct SampleBufs {
     int32_t *flag;     // overflow / zero-total flag
 };
 void sample_sizes(int n, int64_t *nsub, int64_t *nblk, int64_t *nchunk);
+// sym_n > 0: psi is the complement-symmetric layout of sym_n qubits (n =
+// sym_n - 1 stored bits); each drawn z is returned as the full index y(z) or
+// its complement, chosen by bit 63 of word 1 of the same Philox output.
 hipError_t launch_sample(int prec, const void *psi, int n, const SampleBufs &b, uint64_t seed,
-                         int64_t shots, uint64_t *out, hipStream_t st);
+                         int64_t shots, uint64_t *out, hipStream_t st, int sym_n = 0);
 
 // Cut-value histogram.
 constexpr int64_t kHistLdsBytes = 64 << 10;   // private LDS histograms up to 8192 bins
@@ -219,7 +227,10 @@ struct HistGeom {
     bool lds;         // private histograms in LDS
 };
 HistGeom hist_geom(int prec, int n, int nbins);
+// shift: the per-bin sums are multiplied by 2^shift (1 for the complement-symmetric layout,
+// where each stored amplitude stands for two basis states).
 hipError_t launch_histogram(int prec, const void *psi, const int32_t *diag, int nbins, const HistGeom &g,
-                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st);
+                            uint64_t *rows, double *fsum, int32_t *flag, uint64_t *out, hipStream_t st,
+                            int shift = 0);
 
 }  // namespace qs

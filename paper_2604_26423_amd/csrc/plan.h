@@ -15,7 +15,8 @@ namespace qs {
 
 struct PassGeom {
     int c, q0;
-    uint32_t targets;
+    uint32_t targets;     // single-bit factors (tile bits)
+    uint32_t pairs = 0;   // bit e: two-bit factor on tile bits e, e+1
 };
 
 inline int cmin_for(int prec)
@@ -55,22 +56,82 @@ inline std::vector<PassGeom> plan_passes(int n, int prec)
     return v;
 }
 
-// Window sequence covering all target bits, starting from window `start`,
+// Window sequence covering all factors (single target bits, and two-bit
+// factors that need both bits in one window), starting from window `start`,
 // for a kernel with 2^tb threads (windows start at or below tb).
-inline WinSeq plan_windows(int start, uint32_t targets, int T, int tb)
+inline WinSeq plan_windows(int start, uint32_t targets, uint32_t pairs, int T, int tb)
 {
     const int rb = T - tb;
     WinSeq w{};
     w.cnt = 0;
     w.s[w.cnt++] = start;
-    uint32_t done = targets & (((1u << rb) - 1u) << start);
-    while (targets & ~done) {
-        const int low = __builtin_ctz(targets & ~done);
+    auto in_win = [&](int s, uint32_t &t, uint32_t &pr) {
+        t = targets & (((1u << rb) - 1u) << s);
+        pr = pairs & (((1u << (rb - 1)) - 1u) << s);
+    };
+    uint32_t done = 0, pdone = 0;
+    in_win(start, done, pdone);
+    while ((targets & ~done) || (pairs & ~pdone)) {
+        int low = 32;
+        if (targets & ~done) low = __builtin_ctz(targets & ~done);
+        if (pairs & ~pdone) low = std::min(low, __builtin_ctz(pairs & ~pdone));
         const int s = std::min(low, tb);
+        if (w.cnt == kMaxWindows) {  // reported by the plan checker
+            w.cnt = kMaxWindows + 1;
+            return w;
+        }
         w.s[w.cnt++] = s;
-        done |= targets & (((1u << rb) - 1u) << s);
+        uint32_t t, pr;
+        in_win(s, t, pr);
+        done |= t;
+        pdone |= pr;
     }
     return w;
+}
+
+inline WinSeq plan_windows(int start, uint32_t targets, int T, int tb)
+{
+    return plan_windows(start, targets, 0u, T, tb);
+}
+
+// Complement-symmetric storage.  Every state of the circuit satisfies
+// psi(x) = psi(~x) (the cost function is invariant under complementing all
+// bits, and so are |+>^n and the mixer), so only the half with bit n-1 = 0
+// is stored, indexed by z, the "domain-wall" coordinates of y = x mod 2^(n-1):
+//   z_q = y_q XOR y_(q+1)  (q < N-1),  z_(N-1) = y_(N-1),  N = n - 1,
+// i.e. y_q = z_q XOR ... XOR z_(N-1).  In these coordinates X on qubit 0
+// flips z_0; X on qubit q (1 <= q <= N-1) flips z_(q-1) and z_q; and X on
+// qubit n-1, which maps the stored half onto the other half and back through
+// the complement, flips z_(N-1) alone.  So the mixer is n commuting factors
+// exp(-i theta/2 X..) on one or two adjacent z bits, each paired like an RX.
+//
+// Pass 0 is the contiguous low tile: the single factor on z_0 and the pairs
+// (z_(q-1), z_q), q = 1..T-1.  Each strided pass holds the bit below its
+// first pair so that every pair has both bits in the tile; the last pass also
+// holds the single factor on z_(N-1).
+inline std::vector<PassGeom> plan_passes_sym(int n, int prec)
+{
+    const int T = tile_bits(prec);
+    const int N = n - 1;
+    std::vector<PassGeom> v;
+    PassGeom g0{0, 0, 1u, ((1u << (T - 1)) - 1u)};
+    const int rem = N - T;          // pair factors q = T..N-1
+    if (rem <= 0) return v;         // such small states are not supported in this layout
+    v.push_back(g0);
+    const int cap = T - cmin_for(prec) - 1;
+    const int np = (rem + cap - 1) / cap;
+    int qa = T;  // first pair factor (bits qa-1, qa) of the next pass
+    for (int i = 0; i < np; ++i) {
+        const int m = rem / np + (i < rem % np ? 1 : 0);
+        const int c = std::min(T - m - 1, 8);
+        const int q0 = qa + m - (T - c);           // strided bits end at bit qa+m-1
+        const int e0 = c + (qa - 1 - q0);          // tile bit of global bit qa-1
+        PassGeom g{c, q0, 0u, ((1u << m) - 1u) << e0};
+        if (i == np - 1) g.targets = 1u << (T - 1);  // z_(N-1) is the top tile bit
+        v.push_back(g);
+        qa += m;
+    }
+    return v;
 }
 
 struct KSpec {

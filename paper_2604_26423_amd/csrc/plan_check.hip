@@ -38,16 +38,51 @@ struct Report {
 
 uint32_t window_mask(int s, int rb) { return ((1u << rb) - 1u) << s; }
 
-int check_windows(Report &R, const WinSeq &w, uint32_t targets, int T, int tb, const char *what)
+int check_windows(Report &R, const WinSeq &w, uint32_t targets, uint32_t pairs, int T, int tb, const char *what)
 {
     const int rb = T - tb;
     if (w.cnt < 1 || w.cnt > kMaxWindows) return R.fail("%s: %d windows", what, w.cnt);
-    uint32_t cov = 0;
+    uint32_t cov = 0, pcov = 0;
     for (int i = 0; i < w.cnt; ++i) {
         if (w.s[i] < 0 || w.s[i] + rb > T) return R.fail("%s: window %d starts at %d", what, i, w.s[i]);
         cov |= window_mask(w.s[i], rb);
+        pcov |= window_mask(w.s[i], rb - 1);  // pair (e, e+1) inside the window
     }
     if ((cov & targets) != targets) return R.fail("%s: windows miss targets (cover %x, targets %x)", what, cov, targets);
+    if ((pcov & pairs) != pairs) return R.fail("%s: windows miss two-bit factors (cover %x, pairs %x)", what, pcov, pairs);
+    return 0;
+}
+
+// Global index bit of tile bit e in a pass.
+int global_bit(const PassGeom &g, int e) { return e < g.c ? e : g.q0 + (e - g.c); }
+
+// Complement-symmetric plan: the n mixer factors (z0), (z_(j-1), z_j) for
+// j = 1..n-2, and (z_(n-2)) are each applied by exactly one pass.
+int check_sym_factors(Report &R, int n, int T, const std::vector<PassGeom> &geo)
+{
+    const int N = n - 1;
+    std::vector<int> single(N, 0), pair(N, 0);  // pair[q]: factor on global bits (q, q+1)
+    for (size_t i = 0; i < geo.size(); ++i) {
+        const PassGeom &g = geo[i];
+        for (int e = 0; e < T; ++e) {
+            if (g.targets >> e & 1u) {
+                if (e < g.c && i > 0) return R.fail("pass %zu: single factor on a carrier bit", i);
+                single[global_bit(g, e)]++;
+            }
+            if (g.pairs >> e & 1u) {
+                if (e + 1 >= T) return R.fail("pass %zu: pair factor at the top tile bit", i);
+                if (i > 0 && e < g.c) return R.fail("pass %zu: pair factor on a carrier bit", i);
+                const int a = global_bit(g, e), b = global_bit(g, e + 1);
+                if (b != a + 1) return R.fail("pass %zu: pair factor on non-adjacent bits %d, %d", i, a, b);
+                pair[a]++;
+            }
+        }
+    }
+    for (int q = 0; q < N; ++q) {
+        const int want_single = (q == 0 || q == N - 1) ? 1 : 0;
+        if (single[q] != want_single) return R.fail("single factor on z_%d applied %d times", q, single[q]);
+        if (q + 1 < N && pair[q] != 1) return R.fail("pair factor (z_%d, z_%d) applied %d times", q, q + 1, pair[q]);
+    }
     return 0;
 }
 
@@ -70,7 +105,7 @@ int check_layout(Report &R, int s, int T, int tb)
     return 0;
 }
 
-int check_tile_maps(Report &R, int n, int T, int tb, const PassGeom &g, const WinSeq *seqs, int nseq)
+int check_tile_maps(Report &R, int n, int T, int tb, const PassGeom &g, const WinSeq *seqs, int nseq)  // n: stored bits
 {
     const int rb = T - tb, nr = 1 << rb, m = T - g.c;
     const int64_t grid = (int64_t)1 << (n - T), dim = (int64_t)1 << n;
@@ -150,12 +185,52 @@ int check_schedule(Report &R, int P, int p)
 
 }  // namespace
 
-extern "C" int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len)
+namespace {
+int check_sym(Report &R, int n, int prec, int p)
+{
+    const int T = tile_bits(prec);
+    const int N = n - 1;
+    const std::vector<PassGeom> geo = plan_passes_sym(n, prec);
+    if (geo.empty()) return R.fail("no plan for n = %d", n);
+    if (check_sym_factors(R, n, T, geo)) return 1;
+    for (size_t i = 0; i < geo.size(); ++i) {
+        const PassGeom &g = geo[i];
+        if (g.c < 0 || g.c > 8) return R.fail("pass %zu: carrier bits %d", i, g.c);
+        if (i == 0 && (g.c != 0 || g.q0 != 0)) return R.fail("first pass must be the low tile");
+        if (i > 0 && g.q0 < g.c) return R.fail("pass %zu: q0 below the carriers", i);
+        if (g.q0 + (T - g.c) > N) return R.fail("pass %zu: tile beyond the stored bits", i);
+    }
+    for (int tb : {kFwdThreadBits, kAdjThreadBits}) {
+        for (int s = 0; s <= tb; ++s)
+            if (check_layout(R, s, T, tb)) return 1;
+        for (const PassGeom &g : geo) {
+            WinSeq seq[3];
+            seq[0] = plan_windows(tb, g.targets, g.pairs, T, tb);
+            seq[1] = plan_windows(tb, g.targets, g.pairs, T, tb);
+            if (seq[1].cnt > kMaxWindows) return R.fail("pre stage: too many windows");
+            seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, g.pairs, T, tb);
+            if (check_windows(R, seq[0], g.targets, g.pairs, T, tb, "single stage")) return 1;
+            if (check_windows(R, seq[2], g.targets, g.pairs, T, tb, "post stage")) return 1;
+            if (check_tile_maps(R, N, T, tb, g, seq, 3)) return 1;
+        }
+    }
+    return check_schedule(R, (int)geo.size(), p);
+}
+}  // namespace
+
+extern "C" int qs_plan_check(int n, int prec_arg, int p, char *msg, size_t msg_len)
 {
     if (msg && msg_len) msg[0] = 0;
-    if (n < 1 || n > 34 || (prec != 0 && prec != 1) || p < 1) return 2;
+    const int sym = (prec_arg & 16) ? 1 : 0;  // QS_SYM
+    const int prec = prec_arg & ~16;
+    if ((prec != 0 && prec != 1) || p < 1) return 2;
     Report R{msg, msg_len};
     const int T = tile_bits(prec);
+    if (sym) {
+        if (n < T + 2 || n > 35) return 2;
+        return check_sym(R, n, prec, p);
+    }
+    if (n < 1 || n > 34) return 2;
     if (n <= T) return 0;  // single-workgroup path
     const std::vector<PassGeom> geo = plan_passes(n, prec);
     // target qubits partition 0..n-1
@@ -186,8 +261,8 @@ extern "C" int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len)
             seq[0] = plan_windows(tb, g.targets, T, tb);                         // single stage
             seq[1] = plan_windows(tb, g.targets, T, tb);                         // pre stage
             seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, T, tb);   // post stage after pre
-            if (check_windows(R, seq[0], g.targets, T, tb, "single stage")) return 1;
-            if (check_windows(R, seq[2], g.targets, T, tb, "post stage")) return 1;
+            if (check_windows(R, seq[0], g.targets, 0u, T, tb, "single stage")) return 1;
+            if (check_windows(R, seq[2], g.targets, 0u, T, tb, "post stage")) return 1;
             if (check_tile_maps(R, n, T, tb, g, seq, 3)) return 1;
         }
     }

@@ -104,10 +104,10 @@ __global__ void __launch_bounds__(256) reduce_l2_kernel(const double *in, int64_
 
 }  // namespace
 
-hipError_t launch_init_plus(int prec, void *psi, int n, hipStream_t st)
+hipError_t launch_init_plus(int prec, void *psi, int n, int nq, hipStream_t st)
 {
     const int64_t dim = (int64_t)1 << n;
-    const double amp0 = sqrt(ldexp(1.0, -n));
+    const double amp0 = sqrt(ldexp(1.0, -nq));
     if (prec == 0)
         hipLaunchKernelGGL(init_plus_kernel<float2>, dim3((unsigned)elem_grid(dim)), dim3(kElemThreads), 0, st,
                            (float2 *)psi, dim, amp0);

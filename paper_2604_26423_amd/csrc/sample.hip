@@ -22,9 +22,9 @@ constexpr int kChunkBits = 26;   // amplitudes per chunk
 constexpr int kSubPerBlock = 1 << (kBlockBits - kSubBits);            // 128
 constexpr int kBlkPerChunk = 1 << (kChunkBits - kBlockBits);          // 8192
 
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), word 0 of the output for
-// counter (c0, 0, 0, 0) and key (k0, 0).
-__device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t k0)
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), words 0 and 1 of the
+// output for counter (c0, 0, 0, 0) and key (k0, 0).
+__device__ __forceinline__ void philox_words01(uint64_t c0, uint64_t k0, uint64_t &w0, uint64_t &w1)
 {
     const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
     const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
@@ -43,7 +43,15 @@ __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t k0)
         x2 = y2;
         x3 = l0;
     }
-    return x0;
+    w0 = x0;
+    w1 = x1;
+}
+
+__device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t k0)
+{
+    uint64_t w0, w1;
+    philox_words01(c0, k0, w0, w1);
+    return w0;
 }
 
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
@@ -159,12 +167,14 @@ template <typename V>
 __global__ void __launch_bounds__(256) sample_shots_kernel(const V *psi, const uint64_t *sub, const uint64_t *blk,
                                                            const uint64_t *chunk, int64_t nchunk, int64_t nblk,
                                                            uint64_t seed, int64_t shots, uint64_t *out,
-                                                           int32_t *flag)
+                                                           int32_t *flag, int sym_n)
 {
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= shots) return;
     const uint64_t T = chunk[nchunk];
-    uint64_t u = __umul64hi(philox_word0((uint64_t)s, seed), T);
+    uint64_t r0, r1;
+    philox_words01((uint64_t)s, seed, r0, r1);
+    uint64_t u = __umul64hi(r0, T);
     const int64_t c = last_le(chunk, nchunk, u);
     u -= chunk[c];
     const int64_t b0 = c * kBlkPerChunk;
@@ -183,7 +193,13 @@ __global__ void __launch_bounds__(256) sample_shots_kernel(const V *psi, const u
             break;
         }
     }
-    out[s] = (uint64_t)x;
+    uint64_t xo = (uint64_t)x;
+    if (sym_n) {  // z -> y(z) (suffix XOR), or its complement over sym_n bits
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) xo ^= xo >> sh;
+        if (r1 >> 63) xo ^= (~0ull) >> (64 - sym_n);
+    }
+    out[s] = xo;
 }
 
 // n < 13: the whole CDF in LDS, one workgroup.
@@ -248,7 +264,7 @@ void sample_sizes(int n, int64_t *nsub, int64_t *nblk, int64_t *nchunk)
 }
 
 hipError_t launch_sample(int prec, const void *psi, int n, const SampleBufs &b, uint64_t seed, int64_t shots,
-                         uint64_t *out, hipStream_t st)
+                         uint64_t *out, hipStream_t st, int sym_n)
 {
     if (n < kBlockBits) {
         if (prec == 0)
@@ -278,11 +294,11 @@ hipError_t launch_sample(int prec, const void *psi, int n, const SampleBufs &b, 
         if (prec == 0)
             hipLaunchKernelGGL(sample_shots_kernel<float2>, dim3((unsigned)g), dim3(256), 0, st, (const float2 *)psi,
                                (const uint64_t *)b.sub, (const uint64_t *)b.blk, (const uint64_t *)b.chunk, nchunk,
-                               nblk, seed, shots, out, b.flag);
+                               nblk, seed, shots, out, b.flag, sym_n);
         else
             hipLaunchKernelGGL(sample_shots_kernel<double2>, dim3((unsigned)g), dim3(256), 0, st,
                                (const double2 *)psi, (const uint64_t *)b.sub, (const uint64_t *)b.blk,
-                               (const uint64_t *)b.chunk, nchunk, nblk, seed, shots, out, b.flag);
+                               (const uint64_t *)b.chunk, nchunk, nblk, seed, shots, out, b.flag, sym_n);
         e = hipGetLastError();
     }
     return e;

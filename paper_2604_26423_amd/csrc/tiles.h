@@ -99,34 +99,50 @@ __device__ __forceinline__ void for_each_reg(const Addr &a, F &&f)
     for (int r = 0; r < NR; ++r) f(r, a.fast_idx(r));
 }
 
-// Forward butterfly stage: walk the windows of `seq`, applying RX to each
-// target bit once, in the first window that holds it.
+// Factors of a stage inside window w (register bits [w, w + RB)): single
+// targets, and two-bit factors whose both bits lie in the window.
+template <int RB>
+__device__ __forceinline__ uint32_t win_singles(uint32_t targets, int w)
+{
+    return targets & (((1u << RB) - 1u) << w);
+}
+template <int RB>
+__device__ __forceinline__ uint32_t win_pairs(uint32_t pairs, int w)
+{
+    return pairs & (((1u << (RB - 1)) - 1u) << w);
+}
+
+// Forward butterfly stage: walk the windows of `seq`, applying each factor
+// once, in the first window that holds it.
 template <int RB, typename V, int NR>
-__device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq, uint32_t targets,
+__device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq, uint32_t targets, uint32_t pairs,
                                           const RxStage &st, int &cur, int tid)
 {
-    uint32_t done = 0;
+    uint32_t done = 0, pdone = 0;
     for (int i = 0; i < seq.cnt; ++i) {
         const int w = seq.s[i];
         if (w != cur) {
             exchange<RB>(v, lds, cur, w, tid);
             cur = w;
         }
-        const uint32_t mask = targets & (((1u << RB) - 1u) << w) & ~done;
-        stage_rx(v, mask >> w, st, 1);
+        const uint32_t mask = win_singles<RB>(targets, w) & ~done;
+        const uint32_t pm = win_pairs<RB>(pairs, w) & ~pdone;
+        stage_rx(v, mask >> w, pm >> w, st, 1);
         done |= mask;
+        pdone |= pm;
     }
 }
 
 // Reverse stage on psi and lambda together: windows in reverse order; for each
-// target qubit accumulate Im <lam| X_q |psi> (invariant under RX applied to
+// factor accumulate Im <lam| X.. |psi> (invariant under the stage applied to
 // both), then apply RX(-theta) to both.  In tangent form both vectors carry
-// 1/cos^j after j qubits, so the terms are rescaled by cos^(2j).
+// 1/cos^j after j factors, so the terms are rescaled by cos^(2j).
 template <int RB, typename V, int NR>
 __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
-                                            uint32_t targets, const RxStage &st, int &cur, int tid, double &gx)
+                                            uint32_t targets, uint32_t pairs, const RxStage &st, int &cur, int tid,
+                                            double &gx)
 {
-    uint32_t done = 0;
+    uint32_t done = 0, pdone = 0;
     double sc = 1.0;
     const double c2 = st.tan ? st.c * st.c : 1.0;
     for (int i = seq.cnt - 1; i >= 0; --i) {
@@ -136,12 +152,16 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
             exchange<RB>(l, lds, cur, w, tid);
             cur = w;
         }
-        const uint32_t mask = targets & (((1u << RB) - 1u) << w) & ~done;
-        gx += sc * imx_reg_mask(l, p, mask >> w);
-        stage_rx(p, mask >> w, st, -1);
-        stage_rx(l, mask >> w, st, -1);
-        for (uint32_t b = mask; b; b &= b - 1) sc *= c2;
+        const uint32_t mask = win_singles<RB>(targets, w) & ~done;
+        const uint32_t pm = win_pairs<RB>(pairs, w) & ~pdone;
+        double g = imx_reg_mask(l, p, mask >> w);
+        if (pm) g += imx_reg_pairs(l, p, pm >> w);
+        gx += sc * g;
+        stage_rx(p, mask >> w, pm >> w, st, -1);
+        stage_rx(l, mask >> w, pm >> w, st, -1);
+        for (int b = __builtin_popcount(mask) + __builtin_popcount(pm); b > 0; --b) sc *= c2;
         done |= mask;
+        pdone |= pm;
     }
 }
 
@@ -184,13 +204,13 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     } else {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
     }
-    if (pp.has_pre) run_stage<RB>(v, lds, pp.A, pp.targets, pp.pre, cur, tid);
+    if (pp.has_pre) run_stage<RB>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
     if (pp.has_phase) {
         const int levels = pp.phase_levels;
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], phase_factor<V>(tab, levels, dg[r]));
     }
-    if (pp.has_post) run_stage<RB>(v, lds, pp.B, pp.targets, pp.post, cur, tid);
+    if (pp.has_post) run_stage<RB>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     if (!pp.has_phase && pp.factor != 1.0) {
         const R fac = (R)pp.factor;
 #pragma unroll
@@ -225,7 +245,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
     V p[NR], l[NR];
     int cur = opaque(pp.load_win);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) { p[r] = psi[g]; });
-    run_stage<RB>(p, lds, pp.B, pp.targets, pp.post, cur, tid);
+    run_stage<RB>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
         const int32_t C = diag[g];
         p[r] = scale_v(p[r], fpost);
@@ -234,7 +254,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
         acc[2] += pr * (double)C;
         l[r] = scale_v(p[r], (R)((double)C * 0.1));
     });
-    unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.post, cur, tid, acc[0]);
+    unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
                      [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
 }
@@ -285,7 +305,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     int cur = opaque(pp.load_win);
     if (pp.has_post) {
-        unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.post, cur, tid, acc[0]);
+        unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
         if (pp.post.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -309,7 +329,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (pp.has_pre) {
-        unrun_stage<RB>(p, l, lds, pp.A, pp.targets, pp.pre, cur, tid, acc[2]);
+        unrun_stage<RB>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
         if (pp.pre.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {

@@ -67,14 +67,38 @@ def n_from_edges(m: int) -> int:
 
 
 # ---------------------------------------------------------------- simulator
+def sym_z_to_x(z, n: int):
+    """Full basis index y(z) (bit n-1 clear) of complement-symmetric index z:
+    y_q = z_q XOR z_(q+1) XOR ... XOR z_(n-2) (a suffix XOR)."""
+    y = np.asarray(z, dtype=np.uint64).copy()
+    sh = 1
+    while sh < 64:
+        y ^= y >> np.uint64(sh)
+        sh <<= 1
+    return y
+
+
+def sym_x_to_z(x, n: int):
+    """Complement-symmetric index of basis state x (x and ~x share it)."""
+    x = np.asarray(x, dtype=np.uint64)
+    top = (x >> np.uint64(n - 1)) & np.uint64(1)
+    full = np.uint64((1 << n) - 1)
+    y = np.where(top == 1, x ^ full, x)
+    return y ^ (y >> np.uint64(1))
+
+
 class Simulator:
     """One LR-QAOA instance on one GPU: cost diagonal, state, readouts.
 
     Device memory (state, diagonal, optional adjoint vector) is held in torch
     tensors; the HIP stream is torch's current stream at construction.
+    symmetric=True stores only the complement-symmetric half (2^(n-1)
+    amplitudes in z order, see include/qs.h, QS_SYM): half the memory and
+    traffic; results refer to the full state.
     """
 
-    def __init__(self, w_tenths, precision: str = "c64", device: str = "cuda", stream=None):
+    def __init__(self, w_tenths, precision: str = "c64", device: str = "cuda", stream=None,
+                 symmetric: bool = False):
         import torch
         self.torch = torch
         self.w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
@@ -84,12 +108,16 @@ class Simulator:
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         cdt = torch.complex64 if self.prec == _qs.QS_C64 else torch.complex128
-        self.psi = torch.empty(1 << self.n, dtype=cdt, device=self.device)
-        self.diag = torch.empty(1 << self.n, dtype=torch.int32, device=self.device)
+        self.symmetric = bool(symmetric)
+        nst = self.n - 1 if self.symmetric else self.n
+        self.psi = torch.empty(1 << nst, dtype=cdt, device=self.device)
+        self.diag = torch.empty(1 << nst, dtype=torch.int32, device=self.device)
         self.lam: Optional[object] = None
-        self.handle = _qs.qs_alloc(self.n, self.prec, self.psi, self.psi.numel() * self.psi.element_size(),
+        flags = self.prec | (_qs.QS_SYM if self.symmetric else 0)
+        self.handle = _qs.qs_alloc(self.n, flags, self.psi, self.psi.numel() * self.psi.element_size(),
                                    self.stream)
-        self.w_total, self.cmax = _qs.qs_cost_diagonal(self.n, self.w, self.diag, self.stream)
+        diag_fn = _qs.qs_cost_diagonal_sym if self.symmetric else _qs.qs_cost_diagonal
+        self.w_total, self.cmax = diag_fn(self.n, self.w, self.diag, self.stream)
 
     # ---- circuit
     def forward(self, theta_zz, theta_x, readout: bool = True):
@@ -124,7 +152,10 @@ class Simulator:
 
     def shots_ratio(self, shots) -> float:
         """r of eq. (5) from sampled bitstrings."""
-        idx = self.torch.as_tensor(np.asarray(shots, dtype=np.int64), device=self.device)
+        shots = np.asarray(shots, dtype=np.uint64)
+        if self.symmetric:
+            shots = sym_x_to_z(shots, self.n)
+        idx = self.torch.as_tensor(shots.astype(np.int64), device=self.device)
         cuts = self.diag[idx].double().mean().item() / 10.0
         return cuts / (self.cmax / 10.0)
 
@@ -154,6 +185,17 @@ class Simulator:
 
     def state(self):
         return self.psi
+
+    def full_state(self):
+        """The state over all 2^n basis states (a new tensor); for the
+        complement-symmetric layout the stored half is expanded."""
+        if not self.symmetric:
+            return self.psi.clone()
+        torch = self.torch
+        x = torch.arange(1 << self.n, dtype=torch.int64, device=self.device)
+        top = (x >> (self.n - 1)) & 1
+        y = torch.where(top == 1, x ^ ((1 << self.n) - 1), x)
+        return self.psi[y ^ (y >> 1)]
 
     # ---- profiling
     def profile(self, enable: bool = True):

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqs.so")
 
 QS_OK, QS_ERR_ARG, QS_ERR_OOM, QS_ERR_HIP, QS_ERR_RANGE, QS_ERR_STATE = range(6)
 QS_C64, QS_C128 = 0, 1
+QS_SYM = 16          # complement-symmetric layout flag, OR'ed into the precision
 QS_MAX_QUBITS_C64, QS_MAX_QUBITS_C128 = 34, 33
 (QS_KIND_PASS, QS_KIND_PASS_PHASE, QS_KIND_ADJOINT, QS_KIND_EXPECT, QS_KIND_SAMPLE,
  QS_KIND_ELEMENTWISE, QS_KIND_REDUCE, QS_KIND_SMALL, QS_KIND_TURNAROUND, QS_KIND_HISTOGRAM,
@@ -35,7 +36,7 @@ KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "a
 
 # every symbol the public headers declare
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
-           "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_apply_cost_layer", "qs_apply_mixer",
+           "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_cost_diagonal_sym", "qs_apply_cost_layer", "qs_apply_mixer",
            "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad", "qs_batch_free"]
 QS_BATCH_MAX_QUBITS = 30
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "qs_set_stream": ([vp, vp], i32),
         "qs_init_plus": ([vp], i32),
         "qs_cost_diagonal": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
+        "qs_cost_diagonal_sym": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
         "qs_apply_cost_layer": ([vp, vp, i64, dbl], i32),
         "qs_apply_mixer": ([vp, dbl], i32),
         "qs_forward": ([vp, vp, i64, i32, vp, vp, _c_dbl_p, _c_dbl_p], i32),
@@ -171,6 +173,15 @@ def qs_cost_diagonal(n: int, w_tenths, diag_dev, stream=None) -> tuple:
     W, cm = ctypes.c_int64(), ctypes.c_int32()
     _check(lib().qs_cost_diagonal(n, w.ctypes.data if w.size else None, _ptr(diag_dev), ctypes.byref(W),
                                   ctypes.byref(cm), _stream(stream)))
+    return int(W.value), int(cm.value)
+
+
+def qs_cost_diagonal_sym(n: int, w_tenths, diag_dev, stream=None) -> tuple:
+    """Diagonal of the complement-symmetric layout (2^(n-1) entries, z order); returns (W_t, C_max)."""
+    w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
+    W, cm = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().qs_cost_diagonal_sym(n, w.ctypes.data if w.size else None, _ptr(diag_dev), ctypes.byref(W),
+                                      ctypes.byref(cm), _stream(stream)))
     return int(W.value), int(cm.value)
 
 

@@ -139,3 +139,27 @@ def test_batch_validation():
     expect_status(qs.QS_ERR_ARG, qs.qs_batch_create, [(14, 2, w14), (14, 2, bad)], qs.QS_C64, 0)
     expect_status(qs.QS_ERR_ARG, qs.qs_batch_info, None, 0)
     assert qs.lib().qs_batch_forward_grad(None, None, None, None, None, None) == qs.QS_ERR_ARG
+
+
+def test_symmetric_layout_limits():
+    assert qs.qs_state_bytes(35, qs.QS_C64 | qs.QS_SYM) == 128 << 30
+    assert qs.qs_state_bytes(36, qs.QS_C64 | qs.QS_SYM) == 0
+    assert qs.qs_state_bytes(14, qs.QS_C64 | qs.QS_SYM) == 0
+    assert qs.qs_state_bytes(15, qs.QS_C64 | qs.QS_SYM) == (1 << 14) * 8
+    assert qs.qs_state_bytes(14, qs.QS_C128 | qs.QS_SYM) == (1 << 13) * 16
+    assert qs.qs_state_bytes(34, qs.QS_C128 | qs.QS_SYM) == 128 << 30
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 14, qs.QS_C64 | qs.QS_SYM, FAKE, 1 << 20, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_alloc, 20, qs.QS_C64 | qs.QS_SYM, FAKE, 8 << 18, 0)  # needs 8 * 2^19
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_sym, 13, np.ones(78, dtype=np.int32), FAKE, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_sym, 36, np.ones(630, dtype=np.int32), FAKE, 0)
+
+
+@pytest.mark.parametrize("prec", [qs.QS_C64, qs.QS_C128])
+def test_symmetric_pass_plan(prec):
+    """Every mixer factor in z coordinates applied once, windows and tile maps valid."""
+    lo = 15 if prec == qs.QS_C64 else 14
+    for n in range(lo, (35 if prec == qs.QS_C64 else 34) + 1):
+        for p in ((1, 2, 3, 5) if n <= 25 else (1, 3)):
+            rc, msg = qs.qs_plan_check(n, prec | qs.QS_SYM, p)
+            assert rc == 0, (n, p, msg)
+    assert qs.qs_plan_check(lo - 1, prec | qs.QS_SYM, 1)[0] == 2

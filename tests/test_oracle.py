@@ -229,6 +229,63 @@ def test_sampling_single_precision_input_is_promoted():
     assert np.array_equal(a, b)
 
 
+# ---------------------------------------------------------------- complement-symmetric storage
+def test_sym_index_map_and_factor_rule():
+    """z -> y(z) pairs every basis state with its complement exactly once, and
+    X on qubit q moves z by the factor mask (z0 | z_(q-1) z_q | z_(n-2))."""
+    n = 6
+    full = (1 << n) - 1
+    zs = {}
+    for z in range(1 << (n - 1)):
+        y = oracle.sym_y_of_z(n, z)
+        assert y < (1 << (n - 1))
+        zs[y] = z
+        zs[y ^ full] = z
+    assert len(zs) == 1 << n
+    for x in range(1 << n):
+        for q in range(n):
+            mask = 1 if q == 0 else (1 << (n - 2)) if q == n - 1 else 3 << (q - 1)
+            assert zs[x ^ (1 << q)] == zs[x] ^ mask, (x, q)
+
+
+def test_circuit_states_are_complement_symmetric():
+    n = 9
+    w = inst(n, 6)
+    psi = oracle.simulate(n, w, *oracle.gate_angles(*oracle.ramp_midpoint(4, 0.8, 0.4)))
+    comp = np.arange(1 << n) ^ ((1 << n) - 1)
+    assert np.abs(psi - psi[comp]).max() < 1e-13
+    half = oracle.sym_half(psi)
+    for z in (0, 1, 77, 255):
+        assert half[z] == psi[oracle.sym_y_of_z(n, z)]
+
+
+def test_sample_sym_delta_and_complement_bit():
+    n, seed = 8, 99
+    half = np.zeros(1 << (n - 1), dtype=np.complex128)
+    z0 = 45
+    half[z0] = 1.0
+    y = oracle.sym_y_of_z(n, z0)
+    s = oracle.sample_sym(half, n, seed, 400)
+    bits = np.array([int(oracle.philox4x64_10([i, 0, 0, 0], [seed, 0])[1]) >> 63 for i in range(400)])
+    want = np.where(bits == 1, y ^ ((1 << n) - 1), y).astype(np.uint64)
+    assert np.array_equal(s, want) and 0 < bits.sum() < 400
+
+
+def test_sample_sym_distribution_g_test():
+    """Shots from the half state follow |psi(x)|^2 of the full state."""
+    from scipy.stats import chi2
+    n = 8
+    w = inst(n, 7)
+    psi = oracle.simulate(n, w, *oracle.gate_angles(*oracle.ramp_midpoint(3, 0.6, 0.6)))
+    shots = 200000
+    s = oracle.sample_sym(oracle.sym_half(psi), n, 5, shots)
+    obs = np.bincount(s.astype(np.int64), minlength=1 << n)
+    exp = np.abs(psi) ** 2 * shots
+    m = obs > 0
+    G = 2 * np.sum(obs[m] * np.log(obs[m] / exp[m]))
+    assert chi2.sf(G, (1 << n) - 1) > 1e-4
+
+
 # ---------------------------------------------------------------- cut-value histogram
 def test_histogram_uniform_state_counts_the_diagonal():
     """On |+>^n every q(x) is 2^(62-n) exactly, so the histogram is the count

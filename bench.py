@@ -80,6 +80,36 @@ def copy_calibration(torch, gib: int = 4):
     return {"bytes": nbytes, "ms": round(t, 4), "gbs": round(nbytes / (t * 1e-3) / 1e9, 1)}
 
 
+def symmetric_run(torch, Simulator, w, tzz, tx, exp_c_full, stream):
+    """The same workload in the complement-symmetric layout (half state)."""
+    sim = Simulator(w, "c64", symmetric=True)
+    n = sim.n
+    p = len(tzz)
+    tf, ta = [], []
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        e, _ = sim.forward(tzz, tx)
+        e1.record(stream)
+        sim.adjoint(tzz, tx)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tf.append(e0.elapsed_time(e1))
+        ta.append(e1.elapsed_time(e2))
+    t_fwd, t_adj = float(sorted(tf[1:])[1]), float(sorted(ta[1:])[1])
+    log(f"symmetric layout: forward {t_fwd:.1f} ms, forward+adjoint {t_adj:.1f} ms")
+    out = {"forward_ms": round(t_fwd, 3), "forward_plus_adjoint_ms": round(t_adj, 3),
+           "amp_layer_per_s": 2.0 ** n * p / (t_fwd * 1e-3),
+           "state_gib": 2.0 ** (n - 1) * 8 / 2 ** 30,
+           "exp_c_rel_diff_vs_full_layout": abs(e - exp_c_full) / exp_c_full}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream):
     """Forward and forward+adjoint at n = 30 for each depth of the sweep."""
     rows = []
@@ -125,6 +155,7 @@ def main():
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison")
     ap.add_argument("--cpu-n", type=int, default=26, help="qubits of the CPU oracle sample")
     ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
+    ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the simulator does not shard the state across GPUs "
@@ -278,6 +309,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+
+    if not args.no_sym:
+        out["symmetric"] = symmetric_run(torch, Simulator, w, tzz, tx, res["exp_c"], stream)
 
     if args.sweep30:
         out["sweep30"] = sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream)

@@ -47,7 +47,13 @@ template <> __device__ __forceinline__ double2 expi<double2>(double a)
 // not fit in 64 bits.
 __device__ __forceinline__ double prob_fp64(double re, double im)
 {
-    return __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im));
+    // hipcc contracts a * b + c into an FMA by default, also through the
+    // __dmul_rn / __dadd_rn helpers; the rule needs two roundings of the
+    // products and one of the sum
+#pragma clang fp contract(off)
+    const double a = re * re;
+    const double b = im * im;
+    return a + b;
 }
 
 __device__ __forceinline__ uint64_t qmass(double P, int32_t *flag)

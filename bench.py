@@ -153,7 +153,7 @@ def main():
     ap.add_argument("--shots", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison")
-    ap.add_argument("--cpu-n", type=int, default=26, help="qubits of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=27, help="qubits of the CPU oracle sample")
     ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
     ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
     args = ap.parse_args()

@@ -13,9 +13,12 @@
  * theta_zz = 2 gamma, theta_x = -2 beta.
  *
  * Conventions shared by every call
- *   - Qubit q is bit q of the amplitude index; amplitude x of an n-qubit
- *     state sits at element x of a contiguous array of 2^n complex numbers
- *     (interleaved re, im; float for QS_C64, double for QS_C128).
+ *   - Qubit q is bit q of the amplitude index.  An n-qubit state is a
+ *     contiguous array of 2^n complex numbers (interleaved re, im; float for
+ *     QS_C64, double for QS_C128) in which amplitude x sits at element
+ *     qs_layout_index(x), an XOR swizzle of x that spreads the passes over
+ *     the HBM channels (identity for x < 2^13).  Cost diagonals use the same
+ *     layout.  qs_get_amplitudes / qs_set_amplitudes copy in index order.
  *   - Edge weights are integers in tenths (w_ij = w_t / 10), listed for
  *     pairs i<j in lexicographic order (0,1),(0,2),...,(0,n-1),(1,2),...
  *   - The cost diagonal is int32 C_t[x] = 10 * C(x), C(x) the cut value of
@@ -103,8 +106,30 @@ qs_status qs_alloc(int n, int prec, void *dev_buf, size_t buf_bytes, void *hip_s
 /* Release the handle, its scratch and (if library-owned) its amplitudes. */
 qs_status qs_free(qs_state s);
 
-/* Device pointer of the amplitudes (2^n complex numbers). */
+/* Device pointer of the amplitudes (2^n complex numbers, layout of qs_layout_index). */
 qs_status qs_state_ptr(qs_state s, void **dev_ptr);
+
+/*
+ * Element of index x in the state and diagonal layout:
+ *   qs_layout_index(x) = x XOR (f(x >> 13) << 4),
+ * f(y) = (y XOR (y >> 9) XOR (y >> 18) XOR (y >> 27)) & 511, the 9-bit digits
+ * of y folded by XOR.  Tiles of amplitudes 2^q apart for large q (the strided
+ * mixer passes) otherwise put all their memory rows on the same HBM channels.
+ * The map is its own inverse, keeps every aligned run of 16 entries and every
+ * aligned block of 2^13 entries together, and is the identity below 2^13.
+ * Returns -1 for x < 0.
+ */
+int64_t qs_layout_index(int64_t x);
+
+/*
+ * Copy amplitudes [first, first + count) of the state, in index order (z
+ * order for QS_SYM states), to dst or from src: count complex numbers on the
+ * device if on_device (8-byte aligned), else on the host (these calls then
+ * synchronise the stream).
+ * Errors: QS_ERR_ARG (range outside the stored amplitudes, null buffer).
+ */
+qs_status qs_get_amplitudes(qs_state s, int64_t first, int64_t count, void *dst, int on_device);
+qs_status qs_set_amplitudes(qs_state s, int64_t first, int64_t count, const void *src, int on_device);
 
 /* Change the stream used for later work on this state. */
 qs_status qs_set_stream(qs_state s, void *hip_stream);
@@ -115,7 +140,8 @@ qs_status qs_init_plus(qs_state s);
 /*
  * Cost diagonal of eq. (6) on the device.
  * w_tenths: host array of n(n-1)/2 weights in tenths, each in [0, 2^20).
- * diag_dev: caller-owned device array of 2^n int32, written in full.
+ * diag_dev: caller-owned device array of 2^n int32 (layout of
+ *           qs_layout_index), written in full.
  * w_total_tenths (out, host, nullable): W_t.
  * cmax_tenths (out, host, nullable): max_x C_t[x] = 10 * C(x*) of eq. (5).
  * hip_stream: stream to use.  Synchronises it when cmax_tenths is non-null.

@@ -72,6 +72,10 @@ struct ProfRec {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
     hipError_t ensure(size_t need)
     {
         if (need <= bytes) return hipSuccess;
@@ -98,7 +102,7 @@ struct qs_state_s {
     void *psi = nullptr;
     bool own = false;
     hipStream_t stream = nullptr;
-    DevBuf partials, tmp, results, sample, shots_out, lambda, hist;
+    DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer;
     bool prof = false;
     std::vector<ProfRec> recs;
 };
@@ -590,6 +594,7 @@ qs_status qs_free(qs_state s)
     s->results.release();
     s->sample.release();
     s->shots_out.release();
+    s->xfer.release();
     s->lambda.release();
     delete s;
     return QS_OK;
@@ -790,6 +795,44 @@ qs_status qs_sample(qs_state s, uint64_t seed, int64_t shots, uint64_t *out, int
     if (flag == 1) return fail(QS_ERR_STATE, "qs_sample: state has zero norm");
     if (flag == 2) return fail(QS_ERR_STATE, "qs_sample: state norm too large (|a|^2 sums to 4 or more)");
     return QS_OK;
+}
+
+int64_t qs_layout_index(int64_t x) { return x < 0 ? -1 : swz(x); }
+
+namespace {
+qs_status copy_amplitudes(qs_state s, int64_t first, int64_t count, void *buf, int on_device, int to_state,
+                          const char *where)
+{
+    if (qs_status st = check_state(s)) return st;
+    const int64_t dim = (int64_t)1 << s->n;
+    if (first < 0 || count < 0 || first > dim || count > dim - first)
+        return fail(QS_ERR_ARG, "%s: range [%lld, %lld) outside 0..%lld", where, (long long)first,
+                    (long long)(first + count), (long long)dim);
+    if (count > 0 && !buf) return fail(QS_ERR_ARG, "%s: null buffer", where);
+    if (count == 0) return QS_OK;
+    const size_t bytes = (size_t)count * amp_bytes(s->prec);
+    if (on_device) {
+        if (!aligned(buf, 8)) return fail(QS_ERR_ARG, "%s: device buffer must be 8-byte aligned", where);
+        HIPCHK(launch_copy_amplitudes(s->prec, s->psi, first, count, buf, to_state, s->stream), where);
+        return QS_OK;
+    }
+    HIPCHK(s->xfer.ensure(bytes), where);
+    if (to_state) HIPCHK(hipMemcpyAsync(s->xfer.p, buf, bytes, hipMemcpyHostToDevice, s->stream), where);
+    HIPCHK(launch_copy_amplitudes(s->prec, s->psi, first, count, s->xfer.p, to_state, s->stream), where);
+    if (!to_state) HIPCHK(hipMemcpyAsync(buf, s->xfer.p, bytes, hipMemcpyDeviceToHost, s->stream), where);
+    HIPCHK(hipStreamSynchronize(s->stream), where);
+    return QS_OK;
+}
+}  // namespace
+
+qs_status qs_get_amplitudes(qs_state s, int64_t first, int64_t count, void *dst, int on_device)
+{
+    return copy_amplitudes(s, first, count, dst, on_device, 0, "qs_get_amplitudes");
+}
+
+qs_status qs_set_amplitudes(qs_state s, int64_t first, int64_t count, const void *src, int on_device)
+{
+    return copy_amplitudes(s, first, count, const_cast<void *>(src), on_device, 1, "qs_set_amplitudes");
 }
 
 qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, uint64_t *mass, int out_on_device)
@@ -1041,6 +1084,7 @@ qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double
                     s.map[1] = k.phase >= 0 ? 2 + k.phase : -1;
                     s.map[2] = k.pre >= 0 ? 2 + p + k.pre : -1;
                 }
+                s.mode = tile_mode(s.pp, T, kBatchThreadBits);
                 const int64_t ntiles = (int64_t)1 << (n - T);
                 s.tiles_per_chunk = (int)std::min<int64_t>(ntiles, 16);
                 s.chunks = (int)((ntiles + s.tiles_per_chunk - 1) / s.tiles_per_chunk);

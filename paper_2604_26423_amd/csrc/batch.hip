@@ -32,6 +32,31 @@ __device__ __forceinline__ int find_step(const BatchStep *steps, int nsteps, int
     return lo;
 }
 
+// Tiles [t0, t1) of one step, with the stage code path of that step.
+template <typename V, int T, int MODE>
+__device__ __forceinline__ void run_item(const BatchStep &st, int64_t t0, int64_t t1, V *lds, const V *tab,
+                                         double (&acc)[kSlots], int tid)
+{
+    constexpr int NR = TileCfg<V, T, TBB>::NR;
+    const PassProg &pp = st.pp;
+    if (st.kind == 0) {
+        double fa[2] = {0.0, 0.0};
+        for (int64_t t = t0; t < t1; ++t) fwd_tile<V, T, TBB, MODE>(pp, t, lds, tab, fa, tid);
+        acc[0] = fa[0];
+        acc[1] = fa[1];
+    } else if (st.kind == 1) {
+        for (int64_t t = t0; t < t1; ++t) turn_tile<V, T, TBB, MODE>(pp, t, lds, acc, tid);
+    } else {
+        for (int64_t t = t0; t < t1; ++t) {
+            V p[NR], l[NR];
+            int32_t dg[NR];
+            if (pp.has_phase) rev_load_diag<V, T, TBB>(pp, t, dg, tid);
+            rev_load_vectors<V, T, TBB>(pp, t, p, l, tid);
+            rev_tile<V, T, TBB, MODE>(pp, t, p, l, dg, lds, tab, acc, tid);
+        }
+    }
+}
+
 template <typename V, int T>
 __global__ void __launch_bounds__(1 << TBB) batch_kernel(BatchArgs a)
 {
@@ -92,22 +117,8 @@ __global__ void __launch_bounds__(1 << TBB) batch_kernel(BatchArgs a)
         const int64_t t0 = chunk * st.tiles_per_chunk;
         const int64_t t1 = t0 + st.tiles_per_chunk < pp.ntiles ? t0 + st.tiles_per_chunk : pp.ntiles;
         double acc[kSlots] = {0.0, 0.0, 0.0, 0.0};
-        if (st.kind == 0) {
-            double fa[2] = {0.0, 0.0};
-            for (int64_t t = t0; t < t1; ++t) fwd_tile<V, T, TBB>(pp, t, lds, tab, fa, tid);
-            acc[0] = fa[0];
-            acc[1] = fa[1];
-        } else if (st.kind == 1) {
-            for (int64_t t = t0; t < t1; ++t) turn_tile<V, T, TBB>(pp, t, lds, acc, tid);
-        } else {
-            for (int64_t t = t0; t < t1; ++t) {
-                V p[NR], l[NR];
-                int32_t dg[NR];
-                if (pp.has_phase) rev_load_diag<V, T, TBB>(pp, t, dg, tid);
-                rev_load_vectors<V, T, TBB>(pp, t, p, l, tid);
-                rev_tile<V, T, TBB>(pp, t, p, l, dg, lds, tab, acc, tid);
-            }
-        }
+        if (st.mode == kModeTan) run_item<V, T, kModeTan>(st, t0, t1, lds, tab, acc, tid);
+        else run_item<V, T, kModeGeneral>(st, t0, t1, lds, tab, acc, tid);
         block_sum(acc, red, tid, NT);
         if (tid == 0) {
 #pragma unroll

@@ -177,6 +177,49 @@ __device__ __forceinline__ void rxt_reg_pairs(V (&v)[NR], uint32_t pmask, R u)
     if constexpr (NR >= 64) { if (pmask & 16u) rxt_reg_bit2<4>(v, u); }
 }
 
+// Branch-free tangent-form stage on one register window.  Every register bit
+// K gets the update with u_K = u when bit K of mask selects it and u_K = 0
+// (the identity) otherwise.  With no branches between the updates the
+// compiler keeps each amplitude in its registers; behind a runtime branch per
+// bit it would copy the whole array at every join instead.
+template <int K, typename R>
+__device__ __forceinline__ R sel_u(uint32_t mask, R u)
+{
+    return ((mask >> K) & 1u) ? u : R(0);
+}
+
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_all(V (&v)[NR], uint32_t mask, R u)
+{
+    if constexpr (NR > 1) rxt_reg_bit<0>(v, sel_u<0>(mask, u));
+    if constexpr (NR > 2) rxt_reg_bit<1>(v, sel_u<1>(mask, u));
+    if constexpr (NR > 4) rxt_reg_bit<2>(v, sel_u<2>(mask, u));
+    if constexpr (NR > 8) rxt_reg_bit<3>(v, sel_u<3>(mask, u));
+    if constexpr (NR > 16) rxt_reg_bit<4>(v, sel_u<4>(mask, u));
+    if constexpr (NR > 32) rxt_reg_bit<5>(v, sel_u<5>(mask, u));
+}
+
+// Two-bit factors on register bits (K, K+1), K = 0..RB-2, selected by pmask.
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_pairs_all(V (&v)[NR], uint32_t pmask, R u)
+{
+    if constexpr (NR > 2) rxt_reg_bit2<0>(v, sel_u<0>(pmask, u));
+    if constexpr (NR > 4) rxt_reg_bit2<1>(v, sel_u<1>(pmask, u));
+    if constexpr (NR > 8) rxt_reg_bit2<2>(v, sel_u<2>(pmask, u));
+    if constexpr (NR > 16) rxt_reg_bit2<3>(v, sel_u<3>(pmask, u));
+    if constexpr (NR > 32) rxt_reg_bit2<4>(v, sel_u<4>(pmask, u));
+}
+
+// Single factors of the complement-symmetric layout sit only at the lowest or
+// the highest register bit of a window (tile bits 0 and T-1).
+template <typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_ends(V (&v)[NR], uint32_t mask, R u)
+{
+    constexpr int top = __builtin_ctz(NR) - 1;
+    rxt_reg_bit<0>(v, sel_u<0>(mask, u));
+    if constexpr (top > 0) rxt_reg_bit<top>(v, sel_u<top>(mask, u));
+}
+
 // RX of a stage on the register bits in mask (and the two-bit factors in
 // pmask); sign = -1 applies RX(-theta).
 template <typename V, int NR>
@@ -223,6 +266,36 @@ __device__ __forceinline__ double imx_reg_mask(const V (&l)[NR], const V (&p)[NR
     return acc;
 }
 
+// Branch-free sums of Im <lam| X.. |psi> over the selected register bits
+// (weights 0 or 1), in FP64.
+template <int K>
+__device__ __forceinline__ double sel_w(uint32_t mask)
+{
+    return ((mask >> K) & 1u) ? 1.0 : 0.0;
+}
+
+template <typename V, int NR>
+__device__ __forceinline__ double imx_reg_all(const V (&l)[NR], const V (&p)[NR], uint32_t mask)
+{
+    double g = 0.0;
+    if constexpr (NR > 1) g += sel_w<0>(mask) * imx_reg_bit<0>(l, p);
+    if constexpr (NR > 2) g += sel_w<1>(mask) * imx_reg_bit<1>(l, p);
+    if constexpr (NR > 4) g += sel_w<2>(mask) * imx_reg_bit<2>(l, p);
+    if constexpr (NR > 8) g += sel_w<3>(mask) * imx_reg_bit<3>(l, p);
+    if constexpr (NR > 16) g += sel_w<4>(mask) * imx_reg_bit<4>(l, p);
+    if constexpr (NR > 32) g += sel_w<5>(mask) * imx_reg_bit<5>(l, p);
+    return g;
+}
+
+template <typename V, int NR>
+__device__ __forceinline__ double imx_reg_ends(const V (&l)[NR], const V (&p)[NR], uint32_t mask)
+{
+    constexpr int top = __builtin_ctz(NR) - 1;
+    double g = sel_w<0>(mask) * imx_reg_bit<0>(l, p);
+    if constexpr (top > 0) g += sel_w<top>(mask) * imx_reg_bit<top>(l, p);
+    return g;
+}
+
 // Im <lam| X_a X_b |psi> for the two-bit factor on register bits K, K+1.
 template <int K, typename V, int NR>
 __device__ __forceinline__ double imx_reg_bit2(const V (&l)[NR], const V (&p)[NR])
@@ -249,6 +322,18 @@ __device__ __forceinline__ double imx_reg_pairs(const V (&l)[NR], const V (&p)[N
     if constexpr (NR >= 32) { if (pmask & 8u) acc += imx_reg_bit2<3>(l, p); }
     if constexpr (NR >= 64) { if (pmask & 16u) acc += imx_reg_bit2<4>(l, p); }
     return acc;
+}
+
+template <typename V, int NR>
+__device__ __forceinline__ double imx_reg_pairs_all(const V (&l)[NR], const V (&p)[NR], uint32_t pmask)
+{
+    double g = 0.0;
+    if constexpr (NR > 2) g += sel_w<0>(pmask) * imx_reg_bit2<0>(l, p);
+    if constexpr (NR > 4) g += sel_w<1>(pmask) * imx_reg_bit2<1>(l, p);
+    if constexpr (NR > 8) g += sel_w<2>(pmask) * imx_reg_bit2<2>(l, p);
+    if constexpr (NR > 16) g += sel_w<3>(pmask) * imx_reg_bit2<3>(l, p);
+    if constexpr (NR > 32) g += sel_w<4>(pmask) * imx_reg_bit2<4>(l, p);
+    return g;
 }
 
 // LDS slot of tile element e: an XOR swizzle of the low RB bits with the next

@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_main_kernel(const int32_t *
     int best = 0;
     const int4 *low4 = reinterpret_cast<const int4 *>(low);
     int4 *out4 = reinterpret_cast<int4 *>(diag + (xh << kLowBits));
+    const int f4 = (int)(swz_fold(xh) << (kSwzDst - 2));  // swizzled layout, in int4 units
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int sm = (m & 1) * e[10] + ((m >> 1) & 1) * e[11] + ((m >> 2) & 1) * e[12];
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_main_kernel(const int32_t *
         v.y = b + e0 + t.y;
         v.z = b + e1 + t.z;
         v.w = b + e0 + e1 + t.w;
-        out4[idx] = v;
+        out4[idx ^ f4] = v;
         best = max(best, max(max(v.x, v.y), max(v.z, v.w)));
     }
     for (int off = 32; off >= 1; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
@@ -174,6 +175,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_sym_kernel(const int32_t *w
     __syncthreads();
     const int *blks = reinterpret_cast<const int *>(blk);
     int4 *out4 = reinterpret_cast<int4 *>(diag + (zh << kLowBits));
+    const int f4 = (int)(swz_fold(zh) << (kSwzDst - 2));  // swizzled layout, in int4 units
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         const int idx = m * 256 + tid;
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(kDiagThreads) diag_sym_kernel(const int32_t *w
         v.y = blks[(int)suffix_xor(z + 1) ^ flip];
         v.z = blks[(int)suffix_xor(z + 2) ^ flip];
         v.w = blks[(int)suffix_xor(z + 3) ^ flip];
-        out4[idx] = v;
+        out4[idx ^ f4] = v;
     }
     for (int off = 32; off >= 1; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
     if ((tid & 63) == 0) red[tid >> 6] = best;

@@ -95,15 +95,38 @@ __host__ __device__ __forceinline__ int64_t tile_base(int64_t w, int c, int q0, 
     return (wl << c) | (wh << (q0 + m));
 }
 
+// Memory layout of states, adjoint vectors and cost diagonals: entry x is
+// stored at element swz(x) = x ^ (f(x >> 13) << 4), f the XOR of the 9-bit
+// digits of x >> 13.  Tiles whose amplitudes are 2^q0 apart for large q0 would
+// otherwise send all their rows to the same HBM channels; folding the high
+// index bits into bits 4..12 spreads them while keeping 16-entry runs (128 B
+// of complex64) and every aligned 2^13 block intact.  swz is linear over XOR
+// and its own inverse; it is the identity below 2^13 entries.
+constexpr int kSwzSrc = 13, kSwzDst = 4, kSwzWidth = 9;
+
+__host__ __device__ __forceinline__ int64_t swz_fold(int64_t y)
+{
+    y ^= y >> kSwzWidth;
+    y ^= y >> (2 * kSwzWidth);
+    return y & ((1 << kSwzWidth) - 1);
+}
+
+__host__ __device__ __forceinline__ int64_t swz(int64_t x)
+{
+    return x ^ (swz_fold(x >> kSwzSrc) << kSwzDst);
+}
+
 // Global index of (register r, thread) in window s.  Every window starts at
 // or above the carrier bits (s >= c, guaranteed by the pass plan), so its
 // register bits are contiguous global bits and the index is the thread's
-// r = 0 element plus r << sh.
+// r = 0 element plus r << sh; the two parts occupy disjoint bits, so the
+// memory element is swz(tg) ^ swz(r << sh), a per-thread and a uniform part.
 struct Addr {
     int64_t tg;
     int sh;
     bool fast;  // s >= c (checked by the host plan checker)
     __host__ __device__ __forceinline__ int64_t fast_idx(int r) const { return tg + ((int64_t)r << sh); }
+    __host__ __device__ __forceinline__ int64_t mem_idx(int64_t tgs, int r) const { return tgs ^ swz((int64_t)r << sh); }
 };
 
 __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_t base, int c, int q0)
@@ -116,6 +139,9 @@ hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t s
 int phase_table_levels(int64_t W);
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid,
                                hipStream_t st);
+// Stage code path of a pass for a kernel with 2^tb threads: 0 = general,
+// 1 = branch-free tangent form, 2 = the same for the complement-symmetric layout.
+int tile_mode(const PassProg &pp, int T, int tb);
 // Grid of a tile kernel (kind 0 = forward, 1 = turnaround, 2 = reverse pass).
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles);
 
@@ -128,6 +154,7 @@ constexpr int kBatchThreadBits = 9;   // batched tile kernels: 512 threads
 struct BatchStep {
     PassProg pp;
     int kind;             // 0 = forward pass, 1 = turnaround, 2 = reverse pass
+    int mode;             // stage code path (tile_mode)
     int circuit;
     int prev;             // previous step of the same circuit, -1 if none
     int chunks;           // work items of this step
@@ -186,6 +213,10 @@ hipError_t launch_small_adjoint(int prec, const SmallProg &sp, hipStream_t st);
 // |+>: 2^n stored amplitudes, each 2^(-nq/2) (nq = n, or n + 1 in the
 // complement-symmetric layout).
 hipError_t launch_init_plus(int prec, void *psi, int n, int nq, hipStream_t st);
+// Amplitudes [first, first + count) between index order in buf and the state
+// (to_state = 1 writes the state).
+hipError_t launch_copy_amplitudes(int prec, void *psi, int64_t first, int64_t count, void *buf, int to_state,
+                                  hipStream_t st);
 hipError_t launch_cost_layer(int prec, void *psi, const int32_t *diag, int n, int64_t W,
                              double theta, hipStream_t st);
 hipError_t launch_expect(int prec, const void *psi, const int32_t *diag, int n,

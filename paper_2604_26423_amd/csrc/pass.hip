@@ -16,7 +16,7 @@ namespace qs {
 
 namespace {
 
-template <typename V, int T, int TB>
+template <typename V, int T, int TB, int MODE>
 __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
 {
     constexpr int NT = 1 << TB;
@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
     double acc[2] = {0.0, 0.0};
     for (int64_t tile = xcd_tile(pp.xcd_remap); tile < pp.ntiles; tile += gridDim.x)
-        fwd_tile<V, T, TB>(pp, tile, lds, tab, acc, tid);
+        fwd_tile<V, T, TB, MODE>(pp, tile, lds, tab, acc, tid);
     if (pp.readout) {
         block_sum(acc, red, tid, NT);
         if (tid == 0) {
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
 }
 
-template <typename V, int T, int TB, bool turnaround>
+template <typename V, int T, int TB, bool turnaround, int MODE>
 __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
 {
     using Cfg = TileCfg<V, T, TB>;
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
     const int64_t G = gridDim.x;
     int64_t tile = xcd_tile(pp.xcd_remap);
     if constexpr (turnaround) {
-        for (; tile < pp.ntiles; tile += G) turn_tile<V, T, TB>(pp, tile, lds, acc, tid);
+        for (; tile < pp.ntiles; tile += G) turn_tile<V, T, TB, MODE>(pp, tile, lds, acc, tid);
     } else {
         V p[NR], l[NR];
         int32_t dg[NR];
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
 #else
             rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
 #endif
-            rev_tile<V, T, TB>(pp, tile, p, l, dg, lds, tab, acc, tid);
+            rev_tile<V, T, TB, MODE>(pp, tile, p, l, dg, lds, tab, acc, tid);
 #if QS_ADJ_PREFETCH
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -114,27 +114,69 @@ int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
     return ntiles;
 }
 
-hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+// Stage code path of a pass (see tiles.h): branch-free when every stage is in
+// tangent form, and, for the complement-symmetric layout, when every single
+// factor sits at an end of its window.
+int tile_mode(const PassProg &pp, int T, int tb)
+{
+    if ((pp.has_pre && !pp.pre.tan) || (pp.has_post && !pp.post.tan)) return kModeGeneral;
+    if (!pp.pairs) return kModeTan;
+    const int rb = T - tb;
+    auto ends_only = [&](const WinSeq &w) {
+        for (int i = 0; i < w.cnt; ++i) {
+            const uint32_t in = (pp.targets >> w.s[i]) & ((1u << rb) - 1u);
+            if (in & ~(1u | (1u << (rb - 1)))) return false;
+        }
+        return true;
+    };
+    if ((pp.has_pre && !ends_only(pp.A)) || (pp.has_post && !ends_only(pp.B))) return kModeGeneral;
+    return kModeTanSym;
+}
+
+namespace {
+template <int MODE>
+void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     constexpr int FT = kFwdThreadBits;
     if (prec == 0)
-        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT>), dim3((unsigned)grid), dim3(1 << FT), 0, st, pp);
-    else
-        hipLaunchKernelGGL((pass_kernel<double2, kTileBitsC128, FT>), dim3((unsigned)grid), dim3(1 << FT), 0, st,
+        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT, MODE>), dim3((unsigned)grid), dim3(1 << FT), 0, st,
                            pp);
+    else
+        hipLaunchKernelGGL((pass_kernel<double2, kTileBitsC128, FT, MODE>), dim3((unsigned)grid), dim3(1 << FT), 0,
+                           st, pp);
+}
+
+template <int MODE>
+void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
+{
+    constexpr int AT = kAdjThreadBits;
+    const dim3 g((unsigned)grid), b(1 << AT);
+    if (prec == 0) {
+        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, true, MODE>), g, b, 0, st, pp);
+        else hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, false, MODE>), g, b, 0, st, pp);
+    } else {
+        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, true, MODE>), g, b, 0, st, pp);
+        else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, false, MODE>), g, b, 0, st, pp);
+    }
+}
+}  // namespace
+
+hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+{
+    switch (tile_mode(pp, tile_bits(prec), kFwdThreadBits)) {
+    case kModeTan: launch_pass_m<kModeTan>(prec, pp, grid, st); break;
+    case kModeTanSym: launch_pass_m<kModeTanSym>(prec, pp, grid, st); break;
+    default: launch_pass_m<kModeGeneral>(prec, pp, grid, st); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
-    constexpr int AT = kAdjThreadBits;
-    const dim3 g((unsigned)grid), b(1 << AT);
-    if (prec == 0) {
-        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, true>), g, b, 0, st, pp);
-        else hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, false>), g, b, 0, st, pp);
-    } else {
-        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, true>), g, b, 0, st, pp);
-        else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, false>), g, b, 0, st, pp);
+    switch (tile_mode(pp, tile_bits(prec), kAdjThreadBits)) {
+    case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
+    case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;
+    default: launch_adjoint_m<kModeGeneral>(prec, pp, turnaround, grid, st); break;
     }
     return hipGetLastError();
 }

@@ -44,6 +44,8 @@ int check_windows(Report &R, const WinSeq &w, uint32_t targets, uint32_t pairs, 
     if (w.cnt < 1 || w.cnt > kMaxWindows) return R.fail("%s: %d windows", what, w.cnt);
     uint32_t cov = 0, pcov = 0;
     for (int i = 0; i < w.cnt; ++i) {
+        // the branch-free stage code exchanges unconditionally between windows
+        if (i > 0 && w.s[i] == w.s[i - 1]) return R.fail("%s: window %d repeats the previous one", what, i);
         if (w.s[i] < 0 || w.s[i] + rb > T) return R.fail("%s: window %d starts at %d", what, i, w.s[i]);
         cov |= window_mask(w.s[i], rb);
         pcov |= window_mask(w.s[i], rb - 1);  // pair (e, e+1) inside the window
@@ -140,6 +142,8 @@ int check_tile_maps(Report &R, int n, int T, int tb, const PassGeom &g, const Wi
                     for (int r = 0; r < nr; ++r) {
                         const int64_t want = tile_gidx(win_elem(r, tid, s, rb), base, g.c, g.q0);
                         if (a.fast_idx(r) != want) return R.fail("window %d: index map wrong", s);
+                        if (a.mem_idx(swz(a.tg), r) != swz(want)) return R.fail("window %d: swizzled index wrong", s);
+                        if (swz(swz(want)) != want || swz(want) >= dim) return R.fail("swizzle is not an involution of [0, 2^n)");
                     }
                 }
             }

@@ -104,6 +104,38 @@ __global__ void __launch_bounds__(256) reduce_l2_kernel(const double *in, int64_
 
 }  // namespace
 
+namespace {
+// Copies between index order and the swizzled state layout (internal.h).
+template <typename V>
+__global__ void __launch_bounds__(kElemThreads) gather_kernel(const V *psi, int64_t first, int64_t count, V *dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kElemThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kElemThreads)
+        dst[i] = psi[swz(first + i)];
+}
+
+template <typename V>
+__global__ void __launch_bounds__(kElemThreads) scatter_kernel(V *psi, int64_t first, int64_t count, const V *src)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kElemThreads + threadIdx.x; i < count; i += (int64_t)gridDim.x * kElemThreads)
+        psi[swz(first + i)] = src[i];
+}
+}  // namespace
+
+hipError_t launch_copy_amplitudes(int prec, void *psi, int64_t first, int64_t count, void *buf, int to_state,
+                                  hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const dim3 g((unsigned)elem_grid(count)), b(kElemThreads);
+    if (prec == 0) {
+        if (to_state) hipLaunchKernelGGL(scatter_kernel<float2>, g, b, 0, st, (float2 *)psi, first, count, (const float2 *)buf);
+        else hipLaunchKernelGGL(gather_kernel<float2>, g, b, 0, st, (const float2 *)psi, first, count, (float2 *)buf);
+    } else {
+        if (to_state) hipLaunchKernelGGL(scatter_kernel<double2>, g, b, 0, st, (double2 *)psi, first, count, (const double2 *)buf);
+        else hipLaunchKernelGGL(gather_kernel<double2>, g, b, 0, st, (const double2 *)psi, first, count, (double2 *)buf);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_init_plus(int prec, void *psi, int n, int nq, hipStream_t st)
 {
     const int64_t dim = (int64_t)1 << n;

@@ -81,9 +81,10 @@ __global__ void __launch_bounds__(256) sample_blocks_kernel(const V *psi, uint64
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t b = blockIdx.x;
     const V *blkp = psi + (b << kBlockBits);
+    const int fb = (int)(swz_fold(b) << kSwzDst);  // layout of the block's entries (internal.h)
     for (int jj = 0; jj < kSubPerBlock / 4; ++jj) {
         const int j = wave * (kSubPerBlock / 4) + jj;
-        const uint64_t q = qval_of(blkp[j * 64 + lane], flag);
+        const uint64_t q = qval_of(blkp[(j * 64 + lane) ^ fb], flag);
         const uint64_t s = wave_sum_u64(q);
         if (lane == 0) ssum[j] = s;
     }
@@ -184,10 +185,11 @@ __global__ void __launch_bounds__(256) sample_shots_kernel(const V *psi, const u
     const int64_t j = last_le(sub + b * kSubPerBlock, kSubPerBlock, u);
     u -= sub[b * kSubPerBlock + j];
     const int64_t x0 = (b << kBlockBits) + (j << kSubBits);
+    const int64_t fb = swz_fold(b) << kSwzDst;
     uint64_t acc = 0;
     int64_t x = x0 + 63;
     for (int t = 0; t < 64; ++t) {
-        acc += qval_of(psi[x0 + t], flag);
+        acc += qval_of(psi[(x0 + t) ^ fb], flag);
         if (acc > u) {
             x = x0 + t;
             break;

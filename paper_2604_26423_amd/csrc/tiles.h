@@ -91,12 +91,14 @@ __device__ __forceinline__ Geom geom_of(const PassProg &pp)
     return Geom{opaque(pp.c), opaque(pp.q0), opaque(pp.width)};
 }
 
-// Call f(r, global index) for every register r of the window.
+// Call f(r, memory element) for every register r of the window (the
+// element of global index a.fast_idx(r) in the swizzled layout).
 template <int NR, typename F>
 __device__ __forceinline__ void for_each_reg(const Addr &a, F &&f)
 {
+    const int64_t tgs = swz(a.tg);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) f(r, a.fast_idx(r));
+    for (int r = 0; r < NR; ++r) f(r, a.mem_idx(tgs, r));
 }
 
 // Factors of a stage inside window w (register bits [w, w + RB)): single
@@ -112,22 +114,67 @@ __device__ __forceinline__ uint32_t win_pairs(uint32_t pairs, int w)
     return pairs & (((1u << (RB - 1)) - 1u) << w);
 }
 
+// Stage code paths.  kModeGeneral handles any stage with runtime branches per
+// register bit; the tangent modes (every stage of the pass in tangent form)
+// are branch-free: kModeTan for single-qubit factors anywhere in a window,
+// kModeTanSym for the complement-symmetric layout (two-bit factors anywhere,
+// single factors only at the window ends).
+enum : int { kModeGeneral = 0, kModeTan = 1, kModeTanSym = 2 };
+
+template <int MODE, typename V, int NR>
+__device__ __forceinline__ void apply_window(V (&v)[NR], uint32_t mask, uint32_t pmask, const RxStage &st, int sign)
+{
+    if constexpr (MODE == kModeGeneral) {
+        stage_rx(v, mask, pmask, st, sign);
+    } else {
+        using R = typename Real<V>::T;
+        const R u = (R)(sign * st.u);
+        if constexpr (MODE == kModeTan) {
+            rxt_reg_all(v, mask, u);
+        } else {
+            rxt_reg_ends(v, mask, u);
+            rxt_reg_pairs_all(v, pmask, u);
+        }
+    }
+}
+
+template <int MODE, typename V, int NR>
+__device__ __forceinline__ double imx_window(const V (&l)[NR], const V (&p)[NR], uint32_t mask, uint32_t pmask)
+{
+    if constexpr (MODE == kModeGeneral) {
+        double g = imx_reg_mask(l, p, mask);
+        if (pmask) g += imx_reg_pairs(l, p, pmask);
+        return g;
+    } else if constexpr (MODE == kModeTan) {
+        return imx_reg_all(l, p, mask);
+    } else {
+        return imx_reg_ends(l, p, mask) + imx_reg_pairs_all(l, p, pmask);
+    }
+}
+
 // Forward butterfly stage: walk the windows of `seq`, applying each factor
-// once, in the first window that holds it.
-template <int RB, typename V, int NR>
+// once, in the first window that holds it.  The first window of every stage
+// is the current layout and consecutive windows differ (checked on the host),
+// so the branch-free modes exchange unconditionally from the second window on.
+template <int RB, int MODE, typename V, int NR>
 __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq, uint32_t targets, uint32_t pairs,
                                           const RxStage &st, int &cur, int tid)
 {
     uint32_t done = 0, pdone = 0;
     for (int i = 0; i < seq.cnt; ++i) {
         const int w = seq.s[i];
-        if (w != cur) {
+        if constexpr (MODE == kModeGeneral) {
+            if (w != cur) {
+                exchange<RB>(v, lds, cur, w, tid);
+                cur = w;
+            }
+        } else if (i > 0) {
             exchange<RB>(v, lds, cur, w, tid);
             cur = w;
         }
         const uint32_t mask = win_singles<RB>(targets, w) & ~done;
         const uint32_t pm = win_pairs<RB>(pairs, w) & ~pdone;
-        stage_rx(v, mask >> w, pm >> w, st, 1);
+        apply_window<MODE>(v, mask >> w, pm >> w, st, 1);
         done |= mask;
         pdone |= pm;
     }
@@ -137,7 +184,7 @@ __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq,
 // factor accumulate Im <lam| X.. |psi> (invariant under the stage applied to
 // both), then apply RX(-theta) to both.  In tangent form both vectors carry
 // 1/cos^j after j factors, so the terms are rescaled by cos^(2j).
-template <int RB, typename V, int NR>
+template <int RB, int MODE, typename V, int NR>
 __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
                                             uint32_t targets, uint32_t pairs, const RxStage &st, int &cur, int tid,
                                             double &gx)
@@ -147,18 +194,22 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
     const double c2 = st.tan ? st.c * st.c : 1.0;
     for (int i = seq.cnt - 1; i >= 0; --i) {
         const int w = seq.s[i];
-        if (w != cur) {
+        if constexpr (MODE == kModeGeneral) {
+            if (w != cur) {
+                exchange<RB>(p, lds, cur, w, tid);
+                exchange<RB>(l, lds, cur, w, tid);
+                cur = w;
+            }
+        } else if (i < seq.cnt - 1) {
             exchange<RB>(p, lds, cur, w, tid);
             exchange<RB>(l, lds, cur, w, tid);
             cur = w;
         }
         const uint32_t mask = win_singles<RB>(targets, w) & ~done;
         const uint32_t pm = win_pairs<RB>(pairs, w) & ~pdone;
-        double g = imx_reg_mask(l, p, mask >> w);
-        if (pm) g += imx_reg_pairs(l, p, pm >> w);
-        gx += sc * g;
-        stage_rx(p, mask >> w, pm >> w, st, -1);
-        stage_rx(l, mask >> w, pm >> w, st, -1);
+        gx += sc * imx_window<MODE>(l, p, mask >> w, pm >> w);
+        apply_window<MODE>(p, mask >> w, pm >> w, st, -1);
+        apply_window<MODE>(l, mask >> w, pm >> w, st, -1);
         for (int b = __builtin_popcount(mask) + __builtin_popcount(pm); b > 0; --b) sc *= c2;
         done |= mask;
         pdone |= pm;
@@ -179,7 +230,7 @@ __device__ __forceinline__ void load_phase_table(V *tab, const V *src, int level
 }
 
 // Forward pass on one tile; with pp.readout, acc += (sum |a|^2, sum |a|^2 C_t).
-template <typename V, int T, int TB>
+template <typename V, int T, int TB, int MODE = kModeGeneral>
 __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *lds, const V *tab, double (&acc)[2],
                                          int tid)
 {
@@ -204,13 +255,13 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     } else {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
     }
-    if (pp.has_pre) run_stage<RB>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
+    if (pp.has_pre) run_stage<RB, MODE>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
     if (pp.has_phase) {
         const int levels = pp.phase_levels;
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], phase_factor<V>(tab, levels, dg[r]));
     }
-    if (pp.has_post) run_stage<RB>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
+    if (pp.has_post) run_stage<RB, MODE>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     if (!pp.has_phase && pp.factor != 1.0) {
         const R fac = (R)pp.factor;
 #pragma unroll
@@ -230,7 +281,7 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
 // Turnaround on one tile: apply the last forward pass, read out the norm and
 // sum |a|^2 C_t (acc[1], acc[2]), form lambda = C psi, undo the pass on both
 // vectors (acc[0] += gx of the pass's layer) and store lambda only.
-template <typename V, int T, int TB>
+template <typename V, int T, int TB, int MODE = kModeGeneral>
 __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *lds, double (&acc)[kSlots], int tid)
 {
     using Cfg = TileCfg<V, T, TB>;
@@ -245,7 +296,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
     V p[NR], l[NR];
     int cur = opaque(pp.load_win);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) { p[r] = psi[g]; });
-    run_stage<RB>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
+    run_stage<RB, MODE>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
         const int32_t C = diag[g];
         p[r] = scale_v(p[r], fpost);
@@ -254,7 +305,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
         acc[2] += pr * (double)C;
         l[r] = scale_v(p[r], (R)((double)C * 0.1));
     });
-    unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+    unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
                      [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
 }
@@ -290,7 +341,7 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
 // gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
 // first forward pass (init) only accumulates and writes nothing.
-template <typename V, int T, int TB>
+template <typename V, int T, int TB, int MODE = kModeGeneral>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                          V (&l)[TileCfg<V, T, TB>::NR], const int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                          V *lds, const V *tab, double (&acc)[kSlots], int tid)
@@ -305,7 +356,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     int cur = opaque(pp.load_win);
     if (pp.has_post) {
-        unrun_stage<RB>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+        unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
         if (pp.post.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -329,7 +380,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (pp.has_pre) {
-        unrun_stage<RB>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
+        unrun_stage<RB, MODE>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
         if (pp.pre.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {

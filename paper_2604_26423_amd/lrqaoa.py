@@ -155,7 +155,7 @@ class Simulator:
         shots = np.asarray(shots, dtype=np.uint64)
         if self.symmetric:
             shots = sym_x_to_z(shots, self.n)
-        idx = self.torch.as_tensor(shots.astype(np.int64), device=self.device)
+        idx = self.torch.as_tensor(_qs.layout_indices(shots.astype(np.int64)), device=self.device)
         cuts = self.diag[idx].double().mean().item() / 10.0
         return cuts / (self.cmax / 10.0)
 
@@ -184,18 +184,35 @@ class Simulator:
         self.lam = None
 
     def state(self):
+        """The state buffer as stored (layout of qs_layout_index)."""
         return self.psi
+
+    def amplitudes(self):
+        """The stored amplitudes in index order (z order for the symmetric layout), a new device tensor."""
+        out = self.torch.empty_like(self.psi)
+        return _qs.qs_get_amplitudes(self.handle, 0, self.psi.numel(), out)
+
+    def set_amplitudes(self, values):
+        """Overwrite the stored amplitudes from a device tensor in index order."""
+        _qs.qs_set_amplitudes(self.handle, 0, values.to(self.psi.dtype).contiguous())
+
+    def diagonal(self):
+        """The cost diagonal in index order (a read-back through the layout map)."""
+        idx = self.torch.as_tensor(_qs.layout_indices(np.arange(self.diag.numel(), dtype=np.int64)),
+                                   device=self.device)
+        return self.diag[idx]
 
     def full_state(self):
         """The state over all 2^n basis states (a new tensor); for the
         complement-symmetric layout the stored half is expanded."""
+        amps = self.amplitudes()
         if not self.symmetric:
-            return self.psi.clone()
+            return amps
         torch = self.torch
         x = torch.arange(1 << self.n, dtype=torch.int64, device=self.device)
         top = (x >> (self.n - 1)) & 1
         y = torch.where(top == 1, x ^ ((1 << self.n) - 1), x)
-        return self.psi[y ^ (y >> 1)]
+        return amps[y ^ (y >> 1)]
 
     # ---- profiling
     def profile(self, enable: bool = True):

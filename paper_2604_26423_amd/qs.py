@@ -37,7 +37,8 @@ KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "a
 # every symbol the public headers declare
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
            "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_cost_diagonal_sym", "qs_apply_cost_layer", "qs_apply_mixer",
-           "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
+           "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_layout_index", "qs_get_amplitudes",
+           "qs_set_amplitudes", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad", "qs_batch_free"]
 QS_BATCH_MAX_QUBITS = 30
 
@@ -86,6 +87,9 @@ def lib() -> ctypes.CDLL:
         "qs_expect": ([vp, vp, _c_dbl_p, _c_dbl_p], i32),
         "qs_sample": ([vp, u64, i64, vp, i32], i32),
         "qs_cost_histogram": ([vp, vp, i32, vp, i32], i32),
+        "qs_layout_index": ([i64], i64),
+        "qs_get_amplitudes": ([vp, i64, i64, vp, i32], i32),
+        "qs_set_amplitudes": ([vp, i64, i64, vp, i32], i32),
         "qs_adjoint_grad": ([vp, vp, i64, i32, vp, vp, vp, sz, _c_dbl_p, vp, vp], i32),
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
@@ -219,6 +223,42 @@ def qs_sample(s, seed: int, shots: int, out=None) -> np.ndarray:
     host = np.empty(int(shots), dtype=np.uint64)
     _check(lib().qs_sample(s, int(seed), int(shots), host.ctypes.data if shots > 0 else None, 0))
     return host
+
+
+def qs_layout_index(x: int) -> int:
+    return int(lib().qs_layout_index(int(x)))
+
+
+def layout_indices(x):
+    """qs_layout_index for an integer array (the formula of include/qs.h)."""
+    x = np.asarray(x, dtype=np.int64)
+    y = x >> 13
+    y = y ^ (y >> 9)
+    y = y ^ (y >> 18)
+    return x ^ ((y & 511) << 4)
+
+
+def qs_get_amplitudes(s, first: int, count: int, out=None):
+    """Amplitudes [first, first + count) in index order: into a device tensor
+    `out` (returned), else a new host array of the state's complex type."""
+    if out is not None:
+        _check(lib().qs_get_amplitudes(s, int(first), int(count), _ptr(out), 1))
+        return out
+    raise ValueError("pass a device tensor or use qs_get_amplitudes_host")
+
+
+def qs_get_amplitudes_host(s, first: int, count: int, dtype) -> np.ndarray:
+    host = np.empty(int(count), dtype=dtype)
+    _check(lib().qs_get_amplitudes(s, int(first), int(count), host.ctypes.data if count else None, 0))
+    return host
+
+
+def qs_set_amplitudes(s, first: int, src, on_device: bool = True) -> None:
+    if on_device:
+        _check(lib().qs_set_amplitudes(s, int(first), int(src.numel()), _ptr(src), 1))
+    else:
+        a = np.ascontiguousarray(src)
+        _check(lib().qs_set_amplitudes(s, int(first), int(a.size), a.ctypes.data if a.size else None, 0))
 
 
 def qs_cost_histogram(s, diag_dev, nbins: int, out=None) -> np.ndarray:

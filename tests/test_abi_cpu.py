@@ -163,3 +163,20 @@ def test_symmetric_pass_plan(prec):
             rc, msg = qs.qs_plan_check(n, prec | qs.QS_SYM, p)
             assert rc == 0, (n, p, msg)
     assert qs.qs_plan_check(lo - 1, prec | qs.QS_SYM, 1)[0] == 2
+
+
+def test_layout_index_map():
+    """The state layout map: the C function and the binding's array form agree,
+    it is its own inverse, the identity below 2^13, and keeps 16-runs and 2^13 blocks."""
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([np.arange(1 << 14), rng.integers(0, 1 << 35, size=20000)]).astype(np.int64)
+    ys = qs.layout_indices(xs)
+    for x, y in zip(xs[::97], ys[::97]):
+        assert qs.qs_layout_index(int(x)) == int(y)
+    assert np.array_equal(qs.layout_indices(ys), xs)
+    assert np.array_equal(ys[:1 << 13], xs[:1 << 13])
+    assert np.array_equal(ys >> 13, xs >> 13) and np.array_equal(ys & 15, xs & 15)
+    for n in (14, 20):
+        perm = qs.layout_indices(np.arange(1 << n))
+        assert np.array_equal(np.sort(perm), np.arange(1 << n))
+    assert qs.qs_layout_index(-1) == -1

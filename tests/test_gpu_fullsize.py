@@ -60,7 +60,7 @@ def test_cost_diagonal_full_size(n, seed):
     g = GOLDEN[(n, seed)]
     assert W == g["w_total_tenths"] and cmax == g["cmax_tenths"]
     xs = sampled_indices(n, 1_000_000, n)
-    got = diag[torch.as_tensor(xs.astype(np.int64), device="cuda")].cpu().numpy()
+    got = diag[torch.as_tensor(qs.layout_indices(xs.astype(np.int64)), device="cuda")].cpu().numpy()
     assert np.array_equal(got.astype(np.int64), oracle.cut_values(n, w, xs))
     # sum_x C = 2^(n-1) W and sum_x C^2 = 2^(n-2) (W^2 + sum w^2): each edge is
     # cut by half of all x, and any two distinct edges are cut together by a quarter
@@ -74,7 +74,7 @@ def test_cost_diagonal_full_size(n, seed):
 
 
 def test_n32_c64_vs_c128_and_single_layer_closed_form():
-    from paper_2604_26423_amd import Simulator
+    from paper_2604_26423_amd import Simulator, qs
     n = 32
     run = workloads.LARGE
     w = run.weights()
@@ -88,6 +88,7 @@ def test_n32_c64_vs_c128_and_single_layer_closed_form():
     assert abs(e64 - e128) <= 1e-6 * e128
     assert abs(e64 / (s64.cmax / 10) - e128 / (s128.cmax / 10)) <= 1e-6 * e128 / (s128.cmax / 10)
     maxabs, l2 = 0.0, 0.0
+    # both states are in the same (swizzled) layout, so they compare element by element
     for a, b in zip(chunks(s64.psi), chunks(s128.psi)):
         d = a.to(torch.complex128) - b
         maxabs = max(maxabs, float(d.abs().max()))
@@ -95,8 +96,9 @@ def test_n32_c64_vs_c128_and_single_layer_closed_form():
     say(f"  c64 vs c128: max-abs {maxabs:.3e}, L2 {np.sqrt(l2):.3e}, <C> {e64:.9f} / {e128:.9f}")
     assert maxabs <= 1e-5 and np.sqrt(l2) <= 1e-4
     # complement symmetry on sampled x (the circuit commutes with X on every qubit)
-    xs = torch.as_tensor(sampled_indices(n, 100_000, 7).astype(np.int64), device="cuda")
-    comp = xs ^ ((1 << n) - 1)
+    xs_np = sampled_indices(n, 100_000, 7).astype(np.int64)
+    xs = torch.as_tensor(qs.layout_indices(xs_np), device="cuda")
+    comp = torch.as_tensor(qs.layout_indices(xs_np ^ ((1 << n) - 1)), device="cuda")
     assert float((s128.psi[xs] - s128.psi[comp]).abs().max()) <= 1e-12
     del s64
     # single layer: exact <C> and gradient at n = 32 from the closed form
@@ -124,12 +126,12 @@ def test_n32_c64_vs_c128_and_single_layer_closed_form():
 def test_n32_single_layers_closed_forms():
     """One cost layer on |+>: a_x = 2^(-n/2) exp(-i theta (W - 2C_x)/20).
     One mixer on |0>: a_y = cos(t/2)^(n-|y|) (-i sin(t/2))^|y|."""
-    from paper_2604_26423_amd import Simulator
+    from paper_2604_26423_amd import Simulator, qs
     n = 32
     w = workloads.LARGE.weights()
     s = Simulator(w, "c64")
     xs_np = sampled_indices(n, 200_000, 11)
-    xs = torch.as_tensor(xs_np.astype(np.int64), device="cuda")
+    xs = torch.as_tensor(qs.layout_indices(xs_np.astype(np.int64)), device="cuda")
     C = oracle.cut_values(n, w, xs_np).astype(np.float64)
     for theta in (0.71, -2.9, 40.3):
         say(f"cost layer alone, theta={theta}")
@@ -154,7 +156,7 @@ def test_n32_single_layers_closed_forms():
 
 
 def test_n34_forward_and_100k_shots():
-    from paper_2604_26423_amd import Simulator
+    from paper_2604_26423_amd import Simulator, qs
     run = workloads.HUGE
     n = run.n
     w = run.weights()
@@ -174,7 +176,8 @@ def test_n34_forward_and_100k_shots():
     again = s.sample(run.shots, run.seed)
     assert np.array_equal(shots, again)
     cut_t = oracle.cut_values(n, w, shots)
-    assert np.array_equal(cut_t, s.diag[torch.as_tensor(shots.astype(np.int64), device="cuda")].cpu().numpy())
+    idx = torch.as_tensor(qs.layout_indices(shots.astype(np.int64)), device="cuda")
+    assert np.array_equal(cut_t, s.diag[idx].cpu().numpy())
     cuts = cut_t / 10.0
     z = (cuts.mean() - e) / np.sqrt(var / run.shots)
     say(f"  <C> {e:.6f}, shots mean {cuts.mean():.6f}, z = {z:.2f}, r_exact {e / (s.cmax / 10):.6f}")

@@ -36,7 +36,7 @@ def say(*a):
 
 def host_state(sim):
     torch.cuda.synchronize()
-    return sim.psi.cpu().numpy()
+    return sim.amplitudes().cpu().numpy()
 
 
 # ---------------------------------------------------------------- diagonal
@@ -45,7 +45,7 @@ def test_cost_diagonal_bit_exact(n):
     say(f"diag n={n}")
     w = workloads.complete_graph_tenths(n, 100 + n)
     sim = sim_for(w, "c64")
-    got = sim.diag.cpu().numpy()
+    got = sim.diagonal().cpu().numpy()
     want = oracle.cost_diagonal(n, w)
     assert np.array_equal(got, want)
     assert sim.w_total == oracle.weight_total(w)
@@ -57,7 +57,7 @@ def test_cost_diagonal_large_weights():
     n = 16
     w = np.random.default_rng(3).integers(0, 1 << 20, size=n * (n - 1) // 2).astype(np.int32)
     sim = sim_for(w, "c64")
-    assert np.array_equal(sim.diag.cpu().numpy(), oracle.cost_diagonal(n, w))
+    assert np.array_equal(sim.diagonal().cpu().numpy(), oracle.cost_diagonal(n, w))
     assert sim.cmax == oracle.cmax_direct(n, w)
     sim.close()
 
@@ -213,8 +213,9 @@ def test_sampling_delta_state_and_zero_state():
     n = 15
     w = workloads.complete_graph_tenths(n, 2)
     sim = sim_for(w, "c64")
-    sim.psi.zero_()
-    sim.psi[12345] = 1j
+    delta = torch.zeros_like(sim.psi)
+    delta[12345] = 1j
+    sim.set_amplitudes(delta)
     assert np.all(sim.sample(300, 1) == 12345)
     sim.psi.zero_()
     with pytest.raises(qs.QSError) as ei:

@@ -42,13 +42,13 @@ def test_sym_forward_vs_oracle(n, p, precision):
     w = workloads.complete_graph_tenths(n, 500 + n)
     s = Simulator(w, precision, symmetric=True)
     diag_full = oracle.cost_diagonal(n, w)
-    assert np.array_equal(s.diag.cpu().numpy().astype(np.int64), half_of_int(n, diag_full))
+    assert np.array_equal(s.diagonal().cpu().numpy().astype(np.int64), half_of_int(n, diag_full))
     assert s.cmax == int(diag_full.max())
     tzz, tx = angles(p, n)
     e, nrm = s.forward(tzz, tx)
     ref = oracle.simulate(n, w, tzz, tx)
     half = oracle.sym_half(ref)
-    got = s.psi.cpu().numpy().astype(np.complex128)
+    got = s.amplitudes().cpu().numpy().astype(np.complex128)
     tol = 1e-12 if precision == "c128" else 1e-5
     assert np.abs(got - half).max() <= tol
     er, nr = oracle.expect(ref, diag_full)
@@ -72,7 +72,7 @@ def test_sym_separate_ops(precision):
         s.apply_mixer(b)
     half = oracle.sym_half(oracle.simulate(n, w, tzz, tx))
     tol = 1e-12 if precision == "c128" else 1e-5
-    assert np.abs(s.psi.cpu().numpy().astype(np.complex128) - half).max() <= tol
+    assert np.abs(s.amplitudes().cpu().numpy().astype(np.complex128) - half).max() <= tol
     s.close()
 
 
@@ -87,7 +87,7 @@ def test_sym_sampling_bit_exact_on_same_state(n, shots, precision):
     s = Simulator(w, precision, symmetric=True)
     s.forward(*angles(3, n))
     got = s.sample(shots, 1234 + n)
-    want = oracle.sample_sym(s.psi.cpu().numpy(), n, 1234 + n, shots)
+    want = oracle.sample_sym(s.amplitudes().cpu().numpy(), n, 1234 + n, shots)
     assert np.array_equal(got, want)
     dev = s.sample(shots, 1234 + n, on_device=True)
     assert np.array_equal(dev.cpu().numpy().astype(np.uint64), want)

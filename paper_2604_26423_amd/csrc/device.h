@@ -248,7 +248,11 @@ __device__ __forceinline__ double imx_reg_bit(const V (&l)[NR], const V (&p)[NR]
     for (int r = 0; r < NR; ++r)
         if (!(r & (1 << K))) {
             const V l0 = l[r], l1 = l[r | (1 << K)], p0 = p[r], p1 = p[r | (1 << K)];
-            acc += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
+            // one fused multiply-add per product
+            acc = fma(l0.x, p1.y, acc);
+            acc = fma(-l0.y, p1.x, acc);
+            acc = fma(l1.x, p0.y, acc);
+            acc = fma(-l1.y, p0.x, acc);
         }
     return (double)acc;
 }
@@ -307,7 +311,10 @@ __device__ __forceinline__ double imx_reg_bit2(const V (&l)[NR], const V (&p)[NR
         if (!(r & (1 << K))) {
             const int q = r ^ (3 << K);
             const V l0 = l[r], l1 = l[q], p0 = p[r], p1 = p[q];
-            acc += (l0.x * p1.y - l0.y * p1.x) + (l1.x * p0.y - l1.y * p0.x);
+            acc = fma(l0.x, p1.y, acc);
+            acc = fma(-l0.y, p1.x, acc);
+            acc = fma(l1.x, p0.y, acc);
+            acc = fma(-l1.y, p0.x, acc);
         }
     return (double)acc;
 }

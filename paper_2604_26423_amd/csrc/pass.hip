@@ -3,9 +3,9 @@
 // tiles.h; these kernels build the workgroup's phase table, walk tiles and
 // reduce the workgroup's partial sums.
 //
-// Forward passes launch one workgroup per tile.  Reverse passes run one
-// persistent workgroup per CU that loads the next tile's two vectors into
-// registers while it works on the current tile.
+// Forward passes launch one workgroup per tile.  The turnaround and the
+// reverse passes run one persistent workgroup per CU that loads the next
+// tile's vectors into registers while it works on the current tile.
 #include "tiles.h"
 
 #ifndef QS_ADJ_PREFETCH
@@ -57,7 +57,25 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
     const int64_t G = gridDim.x;
     int64_t tile = xcd_tile(pp.xcd_remap);
     if constexpr (turnaround) {
-        for (; tile < pp.ntiles; tile += G) turn_tile<V, T, TB, MODE>(pp, tile, lds, acc, tid);
+        V p[NR];
+        int32_t dg[NR];
+#if QS_ADJ_PREFETCH
+        V np[NR];
+        if (tile < pp.ntiles) turn_load<V, T, TB>(pp, tile, p, tid);
+#endif
+        for (; tile < pp.ntiles; tile += G) {
+            turn_load_diag<V, T, TB>(pp, tile, dg, tid);
+#if QS_ADJ_PREFETCH
+            if (tile + G < pp.ntiles) turn_load<V, T, TB>(pp, tile + G, np, tid);
+#else
+            turn_load<V, T, TB>(pp, tile, p, tid);
+#endif
+            turn_compute<V, T, TB, MODE>(pp, tile, p, dg, lds, acc, tid);
+#if QS_ADJ_PREFETCH
+#pragma unroll
+            for (int r = 0; r < NR; ++r) p[r] = np[r];
+#endif
+        }
     } else {
         V p[NR], l[NR];
         int32_t dg[NR];
@@ -103,7 +121,7 @@ int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
     // workgroups better than a persistent loop (measured on MI355X).
     (void)prec;
 #if QS_ADJ_PREFETCH
-    if (adjoint == 2) {
+    if (adjoint == 1 || adjoint == 2) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

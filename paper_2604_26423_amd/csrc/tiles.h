@@ -97,8 +97,17 @@ template <int NR, typename F>
 __device__ __forceinline__ void for_each_reg(const Addr &a, F &&f)
 {
     const int64_t tgs = swz(a.tg);
+    // The register part is uniform: compute its swizzle on the scalar unit.
+    // readfirstlane also keeps the compiler from merging it into the
+    // per-thread part, which would redo the fold per register in vector ALU.
+    const int sh = __builtin_amdgcn_readfirstlane(a.sh);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) f(r, a.mem_idx(tgs, r));
+    for (int r = 0; r < NR; ++r) {
+        const int64_t o = swz((int64_t)r << sh);
+        const int64_t off = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(o >> 32)) << 32) |
+                                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(o & 0xffffffff)));
+        f(r, tgs ^ off);
+    }
 }
 
 // Factors of a stage inside window w (register bits [w, w + RB)): single
@@ -280,34 +289,70 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
 
 // Turnaround on one tile: apply the last forward pass, read out the norm and
 // sum |a|^2 C_t (acc[1], acc[2]), form lambda = C psi, undo the pass on both
-// vectors (acc[0] += gx of the pass's layer) and store lambda only.
+// vectors (acc[0] += gx of the pass's layer) and store lambda only.  Split
+// into loads (psi in the load layout, the diagonal in the final layout) and
+// the rest, so that a persistent kernel can load the next tile early.
+template <typename V, int T, int TB>
+__device__ __forceinline__ void turn_load(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR], int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    const V *psi = reinterpret_cast<const V *>(pp.psi);
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.load_win), Cfg::RB, base, gg.c, gg.q0),
+                          [&](int r, int64_t g) { p[r] = psi[g]; });
+}
+
+template <typename V, int T, int TB>
+__device__ __forceinline__ void turn_load_diag(const PassProg &pp, int64_t tile, int32_t (&dg)[TileCfg<V, T, TB>::NR],
+                                               int tid)
+{
+    using Cfg = TileCfg<V, T, TB>;
+    const Geom gg = geom_of(pp);
+    const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
+    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.final_win), Cfg::RB, base, gg.c, gg.q0),
+                          [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
+}
+
 template <typename V, int T, int TB, int MODE = kModeGeneral>
-__device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *lds, double (&acc)[kSlots], int tid)
+__device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
+                                             const int32_t (&dg)[TileCfg<V, T, TB>::NR], V *lds,
+                                             double (&acc)[kSlots], int tid)
 {
     using Cfg = TileCfg<V, T, TB>;
     using R = typename Cfg::R;
     constexpr int RB = Cfg::RB, NR = Cfg::NR;
-    const V *psi = reinterpret_cast<const V *>(pp.psi);
     V *lam = reinterpret_cast<V *>(pp.lam);
-    const int32_t *diag = pp.diag;
     const R fpost = (R)pp.fpost;
     const Geom gg = geom_of(pp);
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
-    V p[NR], l[NR];
+    V l[NR];
     int cur = opaque(pp.load_win);
-    for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) { p[r] = psi[g]; });
     run_stage<RB, MODE>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
-    for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
-        const int32_t C = diag[g];
+    // cur is now the final layout, the one the diagonal was loaded in
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int32_t C = dg[r];
         p[r] = scale_v(p[r], fpost);
         const double pr = (double)p[r].x * (double)p[r].x + (double)p[r].y * (double)p[r].y;
         acc[1] += pr;
         acc[2] += pr * (double)C;
         l[r] = scale_v(p[r], (R)((double)C * 0.1));
-    });
+    }
     unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
                      [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
+}
+
+template <typename V, int T, int TB, int MODE = kModeGeneral>
+__device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *lds, double (&acc)[kSlots], int tid)
+{
+    constexpr int NR = TileCfg<V, T, TB>::NR;
+    V p[NR];
+    int32_t dg[NR];
+    turn_load_diag<V, T, TB>(pp, tile, dg, tid);
+    turn_load<V, T, TB>(pp, tile, p, tid);
+    turn_compute<V, T, TB, MODE>(pp, tile, p, dg, lds, acc, tid);
 }
 
 // Reverse pass, loads: psi and lambda of a tile in the pass's load layout, and

@@ -257,7 +257,7 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
  */
 #define QS_BATCH_MAX_QUBITS 30
 
-typedef struct {
+typedef struct qs_circuit {
     int n;                   /* qubits: more than 13 (complex64) / 12 (complex128), at most 30 */
     int p;                   /* layers, >= 1 */
     const int32_t *w_tenths; /* host, n(n-1)/2 weights in tenths (as qs_cost_diagonal) */

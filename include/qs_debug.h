@@ -34,6 +34,20 @@ extern "C" {
  */
 int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len);
 
+/*
+ * Check, on the host, the schedule qs_batch_forward_grad would run for these
+ * circuits (structure from qs.h): every circuit's buffers lie inside one
+ * allocation without overlap; work items are numbered contiguously in step
+ * order; each step's predecessor is the previous step of the same circuit and
+ * all its items carry lower numbers (which is what lets the persistent queue
+ * drain); chunks cover each pass's tiles; table offsets, result slots and the
+ * reduction's per-circuit step lists are in range; each circuit has
+ * 2 (p (P - 1) + 1) - 1 steps.  Returns 0 if every check holds, 1 with a
+ * message otherwise, 2 for invalid arguments.
+ */
+struct qs_circuit;
+int qs_batch_plan_check(int count, const struct qs_circuit *circuits, int prec, char *msg, size_t msg_len);
+
 #ifdef __cplusplus
 }
 #endif

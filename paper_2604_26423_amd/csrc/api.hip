@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/qs.h"
+#include "../../include/qs_debug.h"
 #include "internal.h"
 #include "plan.h"
 
@@ -474,6 +475,130 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
         if (qs_status st = run_reduce(s, grid, map, 1, where)) return st;
     }
     return QS_OK;
+}
+
+// Device-memory layout of a batch: per-circuit state, adjoint vector and
+// diagonal offsets (256-byte aligned) and angle offsets; returns the bytes.
+size_t layout_batch(qs_batch b, int count, const qs_circuit *circuits, int prec)
+{
+    b->count = count;
+    b->prec = prec;
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    int64_t aoff = 0;
+    for (int i = 0; i < count; ++i) {
+        const int n = circuits[i].n;
+        b->n.push_back(n);
+        b->p.push_back(circuits[i].p);
+        b->angle_off.push_back(aoff);
+        aoff += circuits[i].p;
+        b->off_psi.push_back(place(qs_state_bytes(n, prec)));
+        b->off_lam.push_back(place(qs_state_bytes(n, prec)));
+        b->off_diag.push_back(place(((size_t)1 << n) * 4));
+        int64_t W = 0;
+        for (size_t e = 0; e < (size_t)n * (n - 1) / 2; ++e) W += circuits[i].w_tenths[e];
+        b->W.push_back(W);
+    }
+    b->angle_off.push_back(aoff);
+    return off;
+}
+
+struct BatchSchedule {
+    int64_t items = 0, tabs = 0, nres = 0;
+    int nidx = 0;
+};
+
+// The steps of every circuit (forward passes, turnaround, reverse passes) in
+// round order -- step r of every circuit, largest circuits first -- with item
+// numbers, predecessor links, table offsets and the per-circuit step lists
+// used by the reduction.  Host only: pointers into b->mem are computed, never
+// dereferenced.
+BatchSchedule build_batch_schedule(qs_batch b, const double *theta_zz, const double *theta_x)
+{
+    BatchSchedule sch;
+    const int T = tile_bits(b->prec);
+    const int count = b->count;
+    // per-circuit step lists (in the circuit's own order)
+    std::vector<std::vector<BatchStep>> cs(count);
+    for (int c = 0; c < count; ++c) {
+        const int n = b->n[c], p = b->p[c];
+        void *psi = (char *)b->mem + b->off_psi[c];
+        void *lam = (char *)b->mem + b->off_lam[c];
+        const int32_t *diag = (const int32_t *)((char *)b->mem + b->off_diag[c]);
+        const Circuit cc{diag, b->W[c], p, theta_zz + b->angle_off[c], theta_x + b->angle_off[c]};
+        const std::vector<PassGeom> geo = plan_passes(n, b->prec);
+        const std::vector<KSpec> ks = forward_specs((int)geo.size(), p);
+        auto add = [&](const KSpec &k, int kind) {
+            BatchStep s{};
+            s.pp = make_prog_raw(psi, n, b->prec, nullptr, geo[k.pass], k, cc, kBatchThreadBits);
+            s.pp.xcd_remap = 0;
+            s.kind = kind;
+            s.circuit = c;
+            for (int j = 0; j < kSlots; ++j) s.map[j] = -1;
+            if (kind >= 1) s.pp.lam = lam;
+            if (kind == 1) {
+                s.map[0] = 2 + p + k.post;
+                s.map[1] = 0;
+                s.map[2] = 1;
+            } else if (kind == 2) {
+                s.pp.load_win = s.pp.final_win;
+                s.map[0] = k.post >= 0 ? 2 + p + k.post : -1;
+                s.map[1] = k.phase >= 0 ? 2 + k.phase : -1;
+                s.map[2] = k.pre >= 0 ? 2 + p + k.pre : -1;
+            }
+            s.mode = tile_mode(s.pp, T, kBatchThreadBits);
+            const int64_t ntiles = (int64_t)1 << (n - T);
+            s.tiles_per_chunk = (int)std::min<int64_t>(ntiles, 16);
+            s.chunks = (int)((ntiles + s.tiles_per_chunk - 1) / s.tiles_per_chunk);
+            cs[c].push_back(s);
+        };
+        for (size_t i = 0; i + 1 < ks.size(); ++i) add(ks[i], 0);
+        add(ks.back(), 1);
+        for (int i = (int)ks.size() - 2; i >= 0; --i) add(ks[i], 2);
+    }
+    // rounds: step r of every circuit, the largest circuits first
+    std::vector<int> order(count);
+    for (int c = 0; c < count; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const double wx = ldexp((double)cs[x].size(), b->n[x]), wy = ldexp((double)cs[y].size(), b->n[y]);
+        return wx > wy;
+    });
+    size_t maxsteps = 0;
+    for (int c = 0; c < count; ++c) maxsteps = std::max(maxsteps, cs[c].size());
+    b->steps_h.clear();
+    std::vector<std::vector<int>> where_c(count);
+    std::vector<int> last(count, -1);
+    int64_t &items = sch.items, &tabs = sch.tabs;
+    const int tabn = batch_table_entries();
+    for (size_t r = 0; r < maxsteps; ++r)
+        for (int c : order) {
+            if (r >= cs[c].size()) continue;
+            BatchStep s = cs[c][r];
+            s.prev = last[c];
+            s.item0 = items;
+            items += s.chunks;
+            s.tab_off = s.pp.has_phase ? (tabs++) * tabn : -1;
+            last[c] = (int)b->steps_h.size();
+            where_c[c].push_back(last[c]);
+            b->steps_h.push_back(s);
+        }
+    b->idx_h.clear();
+    std::vector<int> coff(count + 1, 0);
+    for (int c = 0; c < count; ++c) {
+        coff[c] = (int)b->idx_h.size();
+        for (int j : where_c[c]) b->idx_h.push_back(j);
+    }
+    coff[count] = (int)b->idx_h.size();
+    sch.nidx = (int)b->idx_h.size();
+    b->idx_h.insert(b->idx_h.end(), coff.begin(), coff.end());
+    b->res_off_h.assign(count + 1, 0);
+    for (int c = 0; c < count; ++c) b->res_off_h[c + 1] = b->res_off_h[c] + 2 + 2 * b->p[c];
+    sch.nres = b->res_off_h[count];
+    return sch;
 }
 
 // ---------------------------------------------------------------- diagonal helpers
@@ -976,30 +1101,8 @@ qs_status qs_batch_create(int count, const qs_circuit *circuits, int prec, void 
         }
         qs_batch b = new qs_batch_s();
         b0 = b;
-        b->count = count;
-        b->prec = prec;
         b->stream = (hipStream_t)hip_stream;
-        size_t off = 0;
-        auto place = [&](size_t bytes) {
-            const size_t o = off;
-            off += (bytes + 255) & ~(size_t)255;
-            return o;
-        };
-        int64_t aoff = 0;
-        for (int i = 0; i < count; ++i) {
-            const int n = circuits[i].n;
-            b->n.push_back(n);
-            b->p.push_back(circuits[i].p);
-            b->angle_off.push_back(aoff);
-            aoff += circuits[i].p;
-            b->off_psi.push_back(place(qs_state_bytes(n, prec)));
-            b->off_lam.push_back(place(qs_state_bytes(n, prec)));
-            b->off_diag.push_back(place(((size_t)1 << n) * 4));
-            int64_t W = 0;
-            for (size_t e = 0; e < (size_t)n * (n - 1) / 2; ++e) W += circuits[i].w_tenths[e];
-            b->W.push_back(W);
-        }
-        b->angle_off.push_back(aoff);
+        const size_t off = layout_batch(b, count, circuits, prec);
         hipError_t he = hipMalloc(&b->mem, off);
         if (he != hipSuccess) {
             delete b0;
@@ -1053,86 +1156,13 @@ qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double
             if (!std::isfinite(theta_zz[k]) || !std::isfinite(theta_x[k]))
                 return fail(QS_ERR_ARG, "non-finite angle at index %lld", (long long)k);
         const char *where = "qs_batch_forward_grad";
-        const int T = tile_bits(b->prec);
         const int count = b->count;
 
-        // per-circuit step lists (in the circuit's own order)
-        std::vector<std::vector<BatchStep>> cs(count);
-        for (int c = 0; c < count; ++c) {
-            const int n = b->n[c], p = b->p[c];
-            void *psi = (char *)b->mem + b->off_psi[c];
-            void *lam = (char *)b->mem + b->off_lam[c];
-            const int32_t *diag = (const int32_t *)((char *)b->mem + b->off_diag[c]);
-            const Circuit cc{diag, b->W[c], p, theta_zz + b->angle_off[c], theta_x + b->angle_off[c]};
-            const std::vector<PassGeom> geo = plan_passes(n, b->prec);
-            const std::vector<KSpec> ks = forward_specs((int)geo.size(), p);
-            auto add = [&](const KSpec &k, int kind) {
-                BatchStep s{};
-                s.pp = make_prog_raw(psi, n, b->prec, nullptr, geo[k.pass], k, cc, kBatchThreadBits);
-                s.pp.xcd_remap = 0;
-                s.kind = kind;
-                s.circuit = c;
-                for (int j = 0; j < kSlots; ++j) s.map[j] = -1;
-                if (kind >= 1) s.pp.lam = lam;
-                if (kind == 1) {
-                    s.map[0] = 2 + p + k.post;
-                    s.map[1] = 0;
-                    s.map[2] = 1;
-                } else if (kind == 2) {
-                    s.pp.load_win = s.pp.final_win;
-                    s.map[0] = k.post >= 0 ? 2 + p + k.post : -1;
-                    s.map[1] = k.phase >= 0 ? 2 + k.phase : -1;
-                    s.map[2] = k.pre >= 0 ? 2 + p + k.pre : -1;
-                }
-                s.mode = tile_mode(s.pp, T, kBatchThreadBits);
-                const int64_t ntiles = (int64_t)1 << (n - T);
-                s.tiles_per_chunk = (int)std::min<int64_t>(ntiles, 16);
-                s.chunks = (int)((ntiles + s.tiles_per_chunk - 1) / s.tiles_per_chunk);
-                cs[c].push_back(s);
-            };
-            for (size_t i = 0; i + 1 < ks.size(); ++i) add(ks[i], 0);
-            add(ks.back(), 1);
-            for (int i = (int)ks.size() - 2; i >= 0; --i) add(ks[i], 2);
-        }
-        // rounds: step r of every circuit, the largest circuits first
-        std::vector<int> order(count);
-        for (int c = 0; c < count; ++c) order[c] = c;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            const double wx = ldexp((double)cs[x].size(), b->n[x]), wy = ldexp((double)cs[y].size(), b->n[y]);
-            return wx > wy;
-        });
-        size_t maxsteps = 0;
-        for (int c = 0; c < count; ++c) maxsteps = std::max(maxsteps, cs[c].size());
-        b->steps_h.clear();
-        std::vector<std::vector<int>> where_c(count);
-        std::vector<int> last(count, -1);
-        int64_t items = 0, tabs = 0;
-        const int tabn = batch_table_entries();
-        for (size_t r = 0; r < maxsteps; ++r)
-            for (int c : order) {
-                if (r >= cs[c].size()) continue;
-                BatchStep s = cs[c][r];
-                s.prev = last[c];
-                s.item0 = items;
-                items += s.chunks;
-                s.tab_off = s.pp.has_phase ? (tabs++) * tabn : -1;
-                last[c] = (int)b->steps_h.size();
-                where_c[c].push_back(last[c]);
-                b->steps_h.push_back(s);
-            }
+        const BatchSchedule sch = build_batch_schedule(b, theta_zz, theta_x);
         const int nsteps = (int)b->steps_h.size();
-        b->idx_h.clear();
-        std::vector<int> coff(count + 1, 0);
-        for (int c = 0; c < count; ++c) {
-            coff[c] = (int)b->idx_h.size();
-            for (int j : where_c[c]) b->idx_h.push_back(j);
-        }
-        coff[count] = (int)b->idx_h.size();
-        const int nidx = (int)b->idx_h.size();
-        b->idx_h.insert(b->idx_h.end(), coff.begin(), coff.end());
-        b->res_off_h.assign(count + 1, 0);
-        for (int c = 0; c < count; ++c) b->res_off_h[c + 1] = b->res_off_h[c] + 2 + 2 * b->p[c];
-        const int64_t nres = b->res_off_h[count];
+        const int64_t items = sch.items, tabs = sch.tabs, nres = sch.nres;
+        const int nidx = sch.nidx;
+        const int tabn = batch_table_entries();
 
         const size_t ab = b->prec == QS_C64 ? 8 : 16;
         HIPCHK(b->steps.ensure(sizeof(BatchStep) * nsteps), where);
@@ -1193,6 +1223,95 @@ qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double
     } catch (...) {
         return fail(QS_ERR_OOM, "qs_batch_forward_grad: host allocation failed");
     }
+}
+
+}  // extern "C"
+
+namespace {
+__attribute__((format(printf, 3, 4))) int plan_fail(char *msg, size_t len, const char *fmt, ...)
+{
+    if (msg && len) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(msg, len, fmt, ap);
+        va_end(ap);
+    }
+    return 1;
+}
+}  // namespace
+
+extern "C" {
+
+int qs_batch_plan_check(int count, const qs_circuit *circuits, int prec, char *msg, size_t msg_len)
+{
+#define bad(...) plan_fail(msg, msg_len, __VA_ARGS__)
+    if (msg && msg_len) msg[0] = 0;
+    if (count < 1 || !circuits || (prec != QS_C64 && prec != QS_C128)) return 2;
+    const int T = tile_bits(prec);
+    for (int i = 0; i < count; ++i)
+        if (circuits[i].n <= T || circuits[i].n > QS_BATCH_MAX_QUBITS || circuits[i].p < 1 || !circuits[i].w_tenths)
+            return 2;
+    qs_batch_s b;
+    const size_t total = layout_batch(&b, count, circuits, prec);
+    b.mem = (void *)(uintptr_t)((uint64_t)1 << 40);  // never dereferenced
+    std::vector<double> tzz(b.angle_off.back(), 0.3), tx(b.angle_off.back(), 0.4);
+    const BatchSchedule sch = build_batch_schedule(&b, tzz.data(), tx.data());
+    const std::vector<BatchStep> &st = b.steps_h;
+    const int nsteps = (int)st.size();
+    const int tabn = batch_table_entries();
+    const char *lo = (const char *)b.mem, *hi = lo + total;
+    // circuit memory: inside the allocation, disjoint, 256-byte aligned
+    for (int c = 0; c < count; ++c) {
+        const size_t sb = qs_state_bytes(b.n[c], prec), db = ((size_t)1 << b.n[c]) * 4;
+        if (b.off_psi[c] % 256 || b.off_lam[c] % 256 || b.off_diag[c] % 256) return bad("circuit %d: misaligned", c);
+        if (b.off_psi[c] + sb > b.off_lam[c] || b.off_lam[c] + sb > b.off_diag[c] || b.off_diag[c] + db > total)
+            return bad("circuit %d: buffers overlap or exceed the allocation", c);
+        if (c + 1 < count && b.off_diag[c] + db > b.off_psi[c + 1]) return bad("circuits %d, %d overlap", c, c + 1);
+    }
+    // items: contiguous in step order; predecessors earlier and of the same circuit
+    int64_t next = 0;
+    std::vector<int> seen(count, 0), lastk(count, -1);
+    for (int i = 0; i < nsteps; ++i) {
+        const BatchStep &s = st[i];
+        if (s.item0 != next) return bad("step %d: items not contiguous", i);
+        next += s.chunks;
+        const int64_t ntiles = (int64_t)1 << (b.n[s.circuit] - T);
+        if (s.tiles_per_chunk < 1 || (int64_t)s.chunks * s.tiles_per_chunk < ntiles ||
+            (int64_t)(s.chunks - 1) * s.tiles_per_chunk >= ntiles)
+            return bad("step %d: chunks do not cover the tiles", i);
+        if (s.pp.ntiles != ntiles) return bad("step %d: tile count", i);
+        if (s.prev != lastk[s.circuit]) return bad("step %d: predecessor %d, expected %d", i, s.prev, lastk[s.circuit]);
+        if (s.prev >= 0 && (st[s.prev].circuit != s.circuit || st[s.prev].item0 + st[s.prev].chunks > s.item0))
+            return bad("step %d: predecessor not strictly earlier", i);
+        if ((s.prev < 0) != (s.pp.init != 0 && s.kind == 0)) return bad("step %d: first step must start from |+>", i);
+        lastk[s.circuit] = i;
+        ++seen[s.circuit];
+        const char *psi = (const char *)s.pp.psi, *dg = (const char *)s.pp.diag;
+        if (psi != lo + b.off_psi[s.circuit] || dg != lo + b.off_diag[s.circuit] ||
+            (s.kind >= 1 && (const char *)s.pp.lam != lo + b.off_lam[s.circuit]) || psi < lo || psi >= hi)
+            return bad("step %d: buffer pointers", i);
+        if (s.pp.has_phase != (s.tab_off >= 0)) return bad("step %d: phase table", i);
+        if (s.tab_off >= 0 && (s.tab_off % tabn || s.tab_off / tabn >= sch.tabs)) return bad("step %d: table offset", i);
+        for (int k = 0; k < kSlots; ++k)
+            if (s.map[k] >= 2 + 2 * b.p[s.circuit]) return bad("step %d: result slot", i);
+        if (s.mode != tile_mode(s.pp, T, kBatchThreadBits)) return bad("step %d: stage mode", i);
+    }
+    if (next != sch.items) return bad("item count");
+    for (int c = 0; c < count; ++c) {
+        const int P = (int)plan_passes(b.n[c], prec).size();
+        const int fwd = b.p[c] * (P - 1) + 1;
+        if (seen[c] != 2 * fwd - 1) return bad("circuit %d: %d steps, expected %d", c, seen[c], 2 * fwd - 1);
+    }
+    // the reduction's per-circuit step lists and result offsets
+    const int *cstep = b.idx_h.data(), *coff = b.idx_h.data() + sch.nidx;
+    for (int c = 0; c < count; ++c) {
+        if (coff[c + 1] - coff[c] != seen[c]) return bad("circuit %d: step list", c);
+        for (int j = coff[c]; j < coff[c + 1]; ++j)
+            if (cstep[j] < 0 || cstep[j] >= nsteps || st[cstep[j]].circuit != c) return bad("circuit %d: step list entry", c);
+        if (b.res_off_h[c + 1] - b.res_off_h[c] != 2 + 2 * b.p[c]) return bad("circuit %d: result offsets", c);
+    }
+#undef bad
+    return 0;
 }
 
 qs_status qs_batch_free(qs_batch b)

@@ -61,7 +61,7 @@ template <typename V, int T>
 __global__ void __launch_bounds__(1 << TBB) batch_kernel(BatchArgs a)
 {
     using Cfg = TileCfg<V, T, TBB>;
-    constexpr int NT = Cfg::NT, NR = Cfg::NR;
+    constexpr int NT = Cfg::NT;
     __shared__ V lds[1 << T];
     __shared__ V tab[kTabMax];
     __shared__ double red[kSlots * (NT / 64)];

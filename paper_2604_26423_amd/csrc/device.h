@@ -343,16 +343,6 @@ __device__ __forceinline__ double imx_reg_pairs_all(const V (&l)[NR], const V (&
     return g;
 }
 
-// LDS slot of tile element e: an XOR swizzle of the low RB bits with the next
-// RB bits, which keeps every window layout free of bank conflicts.  It is
-// linear over GF(2), so the slot of (thread part | register part) is the XOR
-// of the two slots: a per-thread constant and a per-register uniform value.
-template <int RB>
-__host__ __device__ __forceinline__ int lds_slot(int e)
-{
-    return e ^ ((e >> RB) & ((1 << RB) - 1));
-}
-
 // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
 // XCD works on a contiguous range of tiles (neighbouring tiles share L2 lines
 // of the cost diagonal and TLB pages).

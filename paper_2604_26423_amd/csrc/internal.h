@@ -116,6 +116,19 @@ __host__ __device__ __forceinline__ int64_t swz(int64_t x)
     return x ^ (swz_fold(x >> kSwzSrc) << kSwzDst);
 }
 
+// LDS slot of tile element e: an XOR of bits [RB, RB + 5) into the low five
+// bits.  Every window layout of a 256- or 512-thread kernel then puts the 32
+// lanes of each half-wave on distinct banks (checked for 32 and 64 banks of
+// 4 bytes).  The map is linear over GF(2), so the slot of (thread part |
+// register part) is the XOR of the two slots: a per-thread constant and a
+// per-register uniform value; and it is a bijection (bits >= 5 are kept, and
+// bit 4 for RB = 4 depends only on bit 8).
+template <int RB>
+__host__ __device__ __forceinline__ int lds_slot(int e)
+{
+    return e ^ ((e >> RB) & 31);
+}
+
 // Global index of (register r, thread) in window s.  Every window starts at
 // or above the carrier bits (s >= c, guaranteed by the pass plan), so its
 // register bits are contiguous global bits and the index is the thread's

@@ -16,7 +16,7 @@ namespace {
 template <int RB>
 int lds_slot_host(int e)
 {
-    return e ^ ((e >> RB) & ((1 << RB) - 1));
+    return qs::lds_slot<RB>(e);
 }
 
 struct Report {

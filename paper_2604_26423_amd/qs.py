@@ -39,7 +39,8 @@ EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free
            "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_cost_diagonal_sym", "qs_apply_cost_layer", "qs_apply_mixer",
            "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_layout_index", "qs_get_amplitudes",
            "qs_set_amplitudes", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
-           "qs_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad", "qs_batch_free"]
+           "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
+           "qs_batch_free"]
 QS_BATCH_MAX_QUBITS = 30
 
 
@@ -94,6 +95,7 @@ def lib() -> ctypes.CDLL:
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
         "qs_plan_check": ([i32, i32, i32, ctypes.c_char_p, sz], i32),
+        "qs_batch_plan_check": ([i32, vp, i32, ctypes.c_char_p, sz], i32),
         "qs_batch_create": ([i32, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "qs_batch_info": ([vp, i32, _c_i64_p, _c_i32_p, ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
         "qs_batch_forward_grad": ([vp, vp, vp, vp, vp, vp], i32),
@@ -306,6 +308,22 @@ def qs_plan_check(n: int, prec: int, p: int) -> tuple:
 
 
 # ---------------------------------------------------------------- batch
+def _circuits(circuits):
+    keep = [np.ascontiguousarray(np.asarray(w, dtype=np.int32)) for _, _, w in circuits]
+    arr = (QSCircuit * len(circuits))()
+    for i, ((n, p, _), w) in enumerate(zip(circuits, keep)):
+        arr[i].n, arr[i].p, arr[i].w_tenths = int(n), int(p), w.ctypes.data
+    return arr, keep
+
+
+def qs_batch_plan_check(circuits, prec: int) -> tuple:
+    """(status, message) of the host-side check of a batch schedule."""
+    arr, keep = _circuits(circuits)
+    buf = ctypes.create_string_buffer(512)
+    rc = lib().qs_batch_plan_check(len(circuits), ctypes.cast(arr, ctypes.c_void_p), int(prec), buf, 512)
+    return rc, buf.value.decode()
+
+
 def qs_batch_create(circuits, prec: int, stream=None) -> ctypes.c_void_p:
     """circuits: sequence of (n, p, w_tenths)."""
     arr = (QSCircuit * len(circuits))()

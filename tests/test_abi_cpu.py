@@ -180,3 +180,23 @@ def test_layout_index_map():
         perm = qs.layout_indices(np.arange(1 << n))
         assert np.array_equal(np.sort(perm), np.arange(1 << n))
     assert qs.qs_layout_index(-1) == -1
+
+
+@pytest.mark.parametrize("prec", [qs.QS_C64, qs.QS_C128])
+def test_batch_schedule(prec):
+    """The persistent batch queue's schedule (predecessors earlier, items
+    contiguous, chunks cover tiles, buffers disjoint), for the 512-circuit
+    workload and small edge cases."""
+    import workloads
+    items = workloads.batch()
+    circuits = [(it.n, it.p, it.weights()) for it in items]
+    rc, msg = qs.qs_batch_plan_check(circuits, prec)
+    assert rc == 0, msg
+    T = 13 if prec == qs.QS_C64 else 12
+    small = [(T + 1, 1, np.ones((T + 1) * T // 2, dtype=np.int32)),
+             (T + 1, 7, np.ones((T + 1) * T // 2, dtype=np.int32)),
+             (24, 2, np.ones(24 * 23 // 2, dtype=np.int32))]
+    for k in range(1, len(small) + 1):
+        rc, msg = qs.qs_batch_plan_check(small[:k], prec)
+        assert rc == 0, msg
+    assert qs.qs_batch_plan_check([(T, 2, np.ones(T * (T - 1) // 2, dtype=np.int32))], prec)[0] == 2

@@ -110,6 +110,43 @@ def symmetric_run(torch, Simulator, w, tzz, tx, exp_c_full, stream):
     return out
 
 
+def batch_run(torch, workloads, stream):
+    """512 uneven circuits (n = 14..22, p in {3, 5, 10}): forward + adjoint
+    gradient of all of them in one persistent launch."""
+    import numpy as np
+    from paper_2604_26423_amd import Batch
+    items = workloads.batch()
+    inst = [(it.weights(), it.p) for it in items]
+    ang = []
+    for it in items:
+        g = [(k - 0.5) / it.p * it.delta_gamma for k in range(1, it.p + 1)]
+        b = [(1 - (k - 0.5) / it.p) * it.delta_beta for k in range(1, it.p + 1)]
+        ang.append((2.0 * np.asarray(g), -2.0 * np.asarray(b)))
+    bt = Batch(inst, "c64")
+    tzz, tx = [a[0] for a in ang], [a[1] for a in ang]
+    ts = []
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        e, gzz, gx = bt.forward_grad(tzz, tx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    t = float(np.median(ts[1:]))
+    amp_layers = sum(float(1 << it.n) * it.p for it in items)
+    # bytes of the same passes run one circuit at a time (forward passes 16-20 B/amp,
+    # turnaround 20, reverse 32-36): about 2 (P - 1) p + 1 passes of <= 36 B per amplitude
+    log(f"batch: {len(items)} circuits, {amp_layers / 1e9:.2f}e9 amp-layers, forward+adjoint {t:.2f} ms")
+    out = {"circuits": len(items), "forward_plus_adjoint_ms": round(t, 3), "circuits_per_s": len(items) / (t * 1e-3),
+           "amp_layer_per_s_fwd_adj": amp_layers / (t * 1e-3), "mean_r_exact": float(np.mean(
+               [ei / (cm / 10) for ei, cm in zip(e, bt.cmax)]))}
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+    return out
+
+
 def sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream):
     """Forward and forward+adjoint at n = 30 for each depth of the sweep."""
     rows = []
@@ -156,6 +193,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=27, help="qubits of the CPU oracle sample")
     ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
     ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched forward+adjoint")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the simulator does not shard the state across GPUs "
@@ -312,6 +350,9 @@ def main():
 
     if not args.no_sym:
         out["symmetric"] = symmetric_run(torch, Simulator, w, tzz, tx, res["exp_c"], stream)
+
+    if not args.no_batch:
+        out["batch"] = batch_run(torch, workloads, stream)
 
     if args.sweep30:
         out["sweep30"] = sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream)

@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(1 << TBB) batch_kernel(BatchArgs a)
 {
     using Cfg = TileCfg<V, T, TBB>;
     constexpr int NT = Cfg::NT;
-    __shared__ V lds[1 << T];
+    __shared__ V lds[2 << T];  // two tiles for the reverse passes
     __shared__ V tab[kTabMax];
     __shared__ double red[kSlots * (NT / 64)];
     __shared__ int64_t s_item;

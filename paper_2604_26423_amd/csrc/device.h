@@ -374,6 +374,30 @@ __device__ __forceinline__ void exchange(V (&v)[NR], V *lds, int from, int to, i
     for (int r = 0; r < NR; ++r) v[r] = lds[tt ^ lds_slot<RB>(r << to)];
 }
 
+// The same move for two arrays at once through an LDS buffer of two tiles:
+// one pair of barriers instead of two.
+template <int RB, typename V, int NR>
+__device__ __forceinline__ void exchange2(V (&a)[NR], V (&b)[NR], V *lds, int from, int to, int tid)
+{
+    constexpr int TILE = NR << 9;  // 2^(RB + 9): tiles of the 512-thread kernels
+    const int tf = lds_slot<RB>(win_elem(0, tid, from, RB));
+    const int tt = lds_slot<RB>(win_elem(0, tid, to, RB));
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int o = tf ^ lds_slot<RB>(r << from);
+        lds[o] = a[r];
+        lds[TILE + o] = b[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int o = tt ^ lds_slot<RB>(r << to);
+        a[r] = lds[o];
+        b[r] = lds[TILE + o];
+    }
+}
+
 // Deterministic workgroup sum of NV doubles (fixed shuffle tree, then waves in
 // order).  Result valid in thread 0.  `red` holds NV * (blockDim/64) doubles.
 template <int NV>

@@ -6,6 +6,8 @@
 // Forward passes launch one workgroup per tile.  The turnaround and the
 // reverse passes run one persistent workgroup per CU that loads the next
 // tile's vectors into registers while it works on the current tile.
+#include <stdlib.h>
+
 #include "tiles.h"
 
 #ifndef QS_ADJ_PREFETCH
@@ -16,7 +18,7 @@ namespace qs {
 
 namespace {
 
-template <typename V, int T, int TB, int MODE>
+template <typename V, int T, int TB, int MODE, int SH>
 __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
 {
     constexpr int NT = 1 << TB;
@@ -30,7 +32,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
     double acc[2] = {0.0, 0.0};
     for (int64_t tile = xcd_tile(pp.xcd_remap); tile < pp.ntiles; tile += gridDim.x)
-        fwd_tile<V, T, TB, MODE>(pp, tile, lds, tab, acc, tid);
+        fwd_tile<V, T, TB, MODE, SH>(pp, tile, lds, tab, acc, tid);
     if (pp.readout) {
         block_sum(acc, red, tid, NT);
         if (tid == 0) {
@@ -40,12 +42,13 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
 }
 
-template <typename V, int T, int TB, bool turnaround, int MODE>
+template <typename V, int T, int TB, bool turnaround, int MODE, int SH>
 __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
 {
     using Cfg = TileCfg<V, T, TB>;
     constexpr int NT = Cfg::NT, NR = Cfg::NR;
-    __shared__ V lds[1 << T];
+    static_assert(TB == 9, "exchange2 assumes 512-thread tiles");
+    __shared__ V lds[2 << T];  // two tiles: psi and lambda move through LDS together
     __shared__ V tab[kTabMax];
     __shared__ double red[kSlots * (NT / 64)];
     const int tid = threadIdx.x;
@@ -87,13 +90,13 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
             // this tile's diagonal is requested before the next tile's vectors:
             // memory counters retire in order, so the phase step then waits
             // only for these loads
-            if (pp.has_phase) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
+            if (SH >= 0 ? (SH & kShPhase) != 0 : pp.has_phase != 0) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
 #if QS_ADJ_PREFETCH
             if (tile + G < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile + G, np, nl, tid);
 #else
             rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
 #endif
-            rev_tile<V, T, TB, MODE>(pp, tile, p, l, dg, lds, tab, acc, tid);
+            rev_tile<V, T, TB, MODE, SH>(pp, tile, p, l, dg, lds, tab, acc, tid);
 #if QS_ADJ_PREFETCH
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -152,29 +155,69 @@ int tile_mode(const PassProg &pp, int T, int tb)
 }
 
 namespace {
-template <int MODE>
-void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+template <int MODE, int SH>
+void launch_pass_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     constexpr int FT = kFwdThreadBits;
     if (prec == 0)
-        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT, MODE>), dim3((unsigned)grid), dim3(1 << FT), 0, st,
-                           pp);
-    else
-        hipLaunchKernelGGL((pass_kernel<double2, kTileBitsC128, FT, MODE>), dim3((unsigned)grid), dim3(1 << FT), 0,
+        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT, MODE, SH>), dim3((unsigned)grid), dim3(1 << FT), 0,
                            st, pp);
+    else
+        hipLaunchKernelGGL((pass_kernel<double2, kTileBitsC128, FT, MODE, SH>), dim3((unsigned)grid), dim3(1 << FT),
+                           0, st, pp);
+}
+
+// Forward shapes with their own instantiation: the first pass (|+>, phase,
+// stage), a junction (stage, phase, stage) and the last pass (stage and
+// readout); anything else uses the runtime-shape kernel.  (A plain stage was
+// measured 1 ms slower fixed than with the runtime shape at n = 32.)
+// QS_PASS_SHAPES=0 in the environment selects the runtime-shape kernels
+// everywhere (for comparisons).
+int shapes_enabled()
+{
+    static const int on = [] {
+        const char *v = getenv("QS_PASS_SHAPES");
+        return v && v[0] == '0' ? 0 : 1;
+    }();
+    return on;
 }
 
 template <int MODE>
-void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
+void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+{
+    switch (shapes_enabled() ? pass_shape(pp) : -1) {
+    case kShInit | kShPhase | kShPost: launch_pass_s<MODE, kShInit | kShPhase | kShPost>(prec, pp, grid, st); break;
+    case kShPre | kShPhase | kShPost: launch_pass_s<MODE, kShPre | kShPhase | kShPost>(prec, pp, grid, st); break;
+    case kShPost | kShReadout: launch_pass_s<MODE, kShPost | kShReadout>(prec, pp, grid, st); break;
+    default: launch_pass_s<MODE, -1>(prec, pp, grid, st); break;
+    }
+}
+
+template <int MODE, bool TURN, int SH>
+void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     constexpr int AT = kAdjThreadBits;
     const dim3 g((unsigned)grid), b(1 << AT);
-    if (prec == 0) {
-        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, true, MODE>), g, b, 0, st, pp);
-        else hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, false, MODE>), g, b, 0, st, pp);
-    } else {
-        if (turnaround) hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, true, MODE>), g, b, 0, st, pp);
-        else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, false, MODE>), g, b, 0, st, pp);
+    if (prec == 0) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, TURN, MODE, SH>), g, b, 0, st, pp);
+    else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, TURN, MODE, SH>), g, b, 0, st, pp);
+}
+
+// Reverse shapes with their own instantiation: a plain stage and the first
+// forward pass undone (phase of layer 1, no writes).  The junction keeps the
+// runtime shape: fixed, it needs more than 256 registers and spills.
+template <int MODE>
+void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
+{
+    if (turnaround) {
+        launch_adjoint_s<MODE, true, -1>(prec, pp, grid, st);
+        return;
+    }
+    switch (shapes_enabled() ? pass_shape(pp) : -1) {
+    case kShPost: launch_adjoint_s<MODE, false, kShPost>(prec, pp, grid, st); break;
+    case kShInit | kShPhase | kShPost:
+        launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost>(prec, pp, grid, st);
+        break;
+    default: launch_adjoint_s<MODE, false, -1>(prec, pp, grid, st); break;
     }
 }
 }  // namespace
@@ -184,7 +227,7 @@ hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t s
     switch (tile_mode(pp, tile_bits(prec), kFwdThreadBits)) {
     case kModeTan: launch_pass_m<kModeTan>(prec, pp, grid, st); break;
     case kModeTanSym: launch_pass_m<kModeTanSym>(prec, pp, grid, st); break;
-    default: launch_pass_m<kModeGeneral>(prec, pp, grid, st); break;
+    default: launch_pass_s<kModeGeneral, -1>(prec, pp, grid, st); break;
     }
     return hipGetLastError();
 }
@@ -194,7 +237,10 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
     switch (tile_mode(pp, tile_bits(prec), kAdjThreadBits)) {
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;
-    default: launch_adjoint_m<kModeGeneral>(prec, pp, turnaround, grid, st); break;
+    default:
+        if (turnaround) launch_adjoint_s<kModeGeneral, true, -1>(prec, pp, grid, st);
+        else launch_adjoint_s<kModeGeneral, false, -1>(prec, pp, grid, st);
+        break;
     }
     return hipGetLastError();
 }

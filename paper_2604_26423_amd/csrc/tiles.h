@@ -130,6 +130,17 @@ __device__ __forceinline__ uint32_t win_pairs(uint32_t pairs, int w)
 // single factors only at the window ends).
 enum : int { kModeGeneral = 0, kModeTan = 1, kModeTanSym = 2 };
 
+// Pass shapes: which parts a pass has.  A kernel instantiated for a shape
+// (SH >= 0) has no runtime branch on them, so the compiler does not copy the
+// register arrays at their joins; SH = -1 reads them from the PassProg.
+enum : int { kShPre = 1, kShPhase = 2, kShPost = 4, kShInit = 8, kShReadout = 16 };
+
+__host__ __device__ __forceinline__ int pass_shape(const PassProg &pp)
+{
+    return (pp.has_pre ? kShPre : 0) | (pp.has_phase ? kShPhase : 0) | (pp.has_post ? kShPost : 0) |
+           (pp.init ? kShInit : 0) | (pp.readout ? kShReadout : 0);
+}
+
 template <int MODE, typename V, int NR>
 __device__ __forceinline__ void apply_window(V (&v)[NR], uint32_t mask, uint32_t pmask, const RxStage &st, int sign)
 {
@@ -205,13 +216,11 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
         const int w = seq.s[i];
         if constexpr (MODE == kModeGeneral) {
             if (w != cur) {
-                exchange<RB>(p, lds, cur, w, tid);
-                exchange<RB>(l, lds, cur, w, tid);
+                exchange2<RB>(p, l, lds, cur, w, tid);
                 cur = w;
             }
         } else if (i < seq.cnt - 1) {
-            exchange<RB>(p, lds, cur, w, tid);
-            exchange<RB>(l, lds, cur, w, tid);
+            exchange2<RB>(p, l, lds, cur, w, tid);
             cur = w;
         }
         const uint32_t mask = win_singles<RB>(targets, w) & ~done;
@@ -239,17 +248,23 @@ __device__ __forceinline__ void load_phase_table(V *tab, const V *src, int level
 }
 
 // Forward pass on one tile; with pp.readout, acc += (sum |a|^2, sum |a|^2 C_t).
-template <typename V, int T, int TB, int MODE = kModeGeneral>
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1>
 __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *lds, const V *tab, double (&acc)[2],
                                          int tid)
 {
     using Cfg = TileCfg<V, T, TB>;
     using R = typename Cfg::R;
     constexpr int RB = Cfg::RB, NR = Cfg::NR;
+    constexpr bool KS = SH >= 0;
+    const bool has_pre = KS ? (SH & kShPre) != 0 : pp.has_pre != 0;
+    const bool has_phase = KS ? (SH & kShPhase) != 0 : pp.has_phase != 0;
+    const bool has_post = KS ? (SH & kShPost) != 0 : pp.has_post != 0;
+    const bool init = KS ? (SH & kShInit) != 0 : pp.init != 0;
+    const bool readout = KS ? (SH & kShReadout) != 0 : pp.readout != 0;
     V *psi = reinterpret_cast<V *>(pp.psi);
     const int32_t *diag = pp.diag;
-    const bool need_diag = pp.has_phase || pp.readout;
-    const int dwin = pp.has_phase ? pp.phase_win : pp.final_win;
+    const bool need_diag = has_phase || readout;
+    const int dwin = has_phase ? pp.phase_win : pp.final_win;
     const Geom g = geom_of(pp);
     const int64_t base = tile_base(tile, g.c, g.q0, g.m);
     V v[NR];
@@ -258,25 +273,27 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     if (need_diag)
         for_each_reg<NR>(win_addr(tid, opaque(dwin), RB, base, g.c, g.q0), [&](int r, int64_t x) { dg[r] = diag[x]; });
     int cur = opaque(pp.load_win);
-    if (pp.init) {
+    if (init) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = V{(R)pp.amp0, (R)0};
     } else {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
     }
-    if (pp.has_pre) run_stage<RB, MODE>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
-    if (pp.has_phase) {
+    if (has_pre) run_stage<RB, MODE>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
+    if (has_phase) {
         const int levels = pp.phase_levels;
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], phase_factor<V>(tab, levels, dg[r]));
     }
-    if (pp.has_post) run_stage<RB, MODE>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
-    if (!pp.has_phase && pp.factor != 1.0) {
+    if (has_post) run_stage<RB, MODE>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
+    // tangent-form factor of a pass without a phase table (scaling by 1 when
+    // it is 1 costs less than a branch in a fixed-shape kernel)
+    if (!has_phase && (KS || pp.factor != 1.0)) {
         const R fac = (R)pp.factor;
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = scale_v(v[r], fac);
     }
-    if (pp.readout) {
+    if (readout) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const double pr = (double)v[r].x * (double)v[r].x + (double)v[r].y * (double)v[r].y;
@@ -386,7 +403,7 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
 // gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
 // first forward pass (init) only accumulates and writes nothing.
-template <typename V, int T, int TB, int MODE = kModeGeneral>
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                          V (&l)[TileCfg<V, T, TB>::NR], const int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                          V *lds, const V *tab, double (&acc)[kSlots], int tid)
@@ -394,15 +411,21 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     using Cfg = TileCfg<V, T, TB>;
     using R = typename Cfg::R;
     constexpr int RB = Cfg::RB, NR = Cfg::NR;
+    constexpr bool KS = SH >= 0;
+    constexpr bool TAN = MODE != kModeGeneral;  // every stage in tangent form
+    const bool has_pre = KS ? (SH & kShPre) != 0 : pp.has_pre != 0;
+    const bool has_phase = KS ? (SH & kShPhase) != 0 : pp.has_phase != 0;
+    const bool has_post = KS ? (SH & kShPost) != 0 : pp.has_post != 0;
+    const bool init = KS ? (SH & kShInit) != 0 : pp.init != 0;
     V *psi = reinterpret_cast<V *>(pp.psi);
     V *lam = reinterpret_cast<V *>(pp.lam);
     const R fpre = (R)pp.fpre, fpost = (R)pp.fpost;
     const Geom gg = geom_of(pp);
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     int cur = opaque(pp.load_win);
-    if (pp.has_post) {
+    if (has_post) {
         unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
-        if (pp.post.tan) {
+        if (TAN || pp.post.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 p[r] = scale_v(p[r], fpost);
@@ -410,23 +433,26 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
             }
         }
     }
-    if (pp.has_phase) {
+    if (has_phase) {
         const int levels = pp.phase_levels;
+        R gz = 0;  // sum of C Im(conj(l) p) over the thread's amplitudes
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const int32_t C = dg[r];
-            const R im = l[r].x * p[r].y - l[r].y * p[r].x;
-            acc[1] += -0.2 * (double)C * (double)im;
-            if (!pp.init) {
+            R im = l[r].x * p[r].y;
+            im = fma(-l[r].y, p[r].x, im);
+            gz = fma((R)C, im, gz);
+            if (!init) {
                 const V f = conj_v(phase_factor<V>(tab, levels, C));
                 p[r] = cmul(p[r], f);
                 l[r] = cmul(l[r], f);
             }
         }
+        acc[1] += -0.2 * (double)gz;
     }
-    if (pp.has_pre) {
+    if (has_pre) {
         unrun_stage<RB, MODE>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
-        if (pp.pre.tan) {
+        if (TAN || pp.pre.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 p[r] = scale_v(p[r], fpre);
@@ -434,7 +460,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
             }
         }
     }
-    if (!pp.init) {
+    if (!init) {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
             psi[g] = p[r];
             lam[g] = l[r];

@@ -79,6 +79,10 @@ def test_full_uneven_batch():
     assert np.all(np.isfinite(e))
     for i in range(len(items)):
         assert 0 <= e[i] <= b.w_total[i] / 10
+    # The batched kernel runs 512-thread tiles, the single-circuit forward
+    # 256-thread ones: the same arithmetic in a different rounding order, so
+    # the two complex64 results agree to the complex64 gradient accuracy
+    # (1e-4 of the largest component, as against the FP64 oracle).
     rng = np.random.default_rng(0)
     for i in sorted(rng.choice(len(items), size=16, replace=False)):
         sim = Simulator(inst[i][0], "c64")
@@ -86,5 +90,5 @@ def test_full_uneven_batch():
         sim.close()
         scale = max(np.abs(szz).max(), np.abs(sx).max())
         assert abs(e[i] - es) <= 2e-5 * es
-        assert np.abs(gzz[i] - szz).max() <= 2e-5 * scale and np.abs(gx[i] - sx).max() <= 2e-5 * scale
+        assert np.abs(gzz[i] - szz).max() <= 1e-4 * scale and np.abs(gx[i] - sx).max() <= 1e-4 * scale
     b.close()

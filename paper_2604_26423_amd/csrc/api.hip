@@ -241,7 +241,7 @@ qs_status launch_tiles(qs_state s, PassProg &pp, int adjoint, int turnaround, in
                        int64_t *grid_out, const char *where)
 {
     // adjoint: 0 = forward pass, 1 = turnaround, 2 = reverse pass
-    const int64_t grid = pass_grid(s->prec, adjoint, pp.ntiles);
+    const int64_t grid = tile_grid(s->prec, adjoint, pp);
     pp.xcd_remap = (grid % 8 == 0) ? 1 : 0;
     Launch L(s, kind, bytes);
     HIPCHK(adjoint ? launch_adjoint_pass(s->prec, pp, turnaround, grid, s->stream)
@@ -441,7 +441,7 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     const std::vector<PassGeom> geo = plan_for(s);
     const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     const int64_t ntiles = (int64_t)1 << (s->n - T);
-    HIPCHK(ensure_partials(s, std::max(pass_grid(s->prec, 0, ntiles), pass_grid(s->prec, 1, ntiles))), where);
+    HIPCHK(ensure_partials(s, ntiles), where);  // no tile kernel has more workgroups than tiles
     const double dim = ldexp(1.0, s->n), ab = (double)amp_bytes(s->prec);
     int64_t grid = 0;
 

@@ -155,8 +155,10 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
 // Stage code path of a pass for a kernel with 2^tb threads: 0 = general,
 // 1 = branch-free tangent form, 2 = the same for the complement-symmetric layout.
 int tile_mode(const PassProg &pp, int T, int tb);
-// Grid of a tile kernel (kind 0 = forward, 1 = turnaround, 2 = reverse pass).
+// Grid of a tile kernel (kind 0 = forward, 1 = turnaround, 2 = reverse pass):
+// the largest one of that kind, and the one launched for a given pass.
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles);
+int64_t tile_grid(int prec, int adjoint, const PassProg &pp);
 
 // ---- batched circuits: one persistent launch over a ticket queue ----
 constexpr int kBatchThreadBits = 9;   // batched tile kernels: 512 threads

@@ -42,13 +42,20 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
 }
 
-template <typename V, int T, int TB, bool turnaround, int MODE, int SH>
-__global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
+// ONE = false: persistent (one workgroup per CU), prefetching the next
+// tile's vectors, psi and lambda exchanged together through a two-tile LDS
+// buffer.  ONE = true: one tile per workgroup, no prefetch, one-tile LDS
+// buffer, at most 128 registers (launch bounds), so that two workgroups share
+// a CU and overlap each other's memory and compute phases.
+template <typename V, int T, int TB, bool turnaround, int MODE, int SH, bool ONE>
+__global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg pp)
 {
     using Cfg = TileCfg<V, T, TB>;
     constexpr int NT = Cfg::NT, NR = Cfg::NR;
+    constexpr bool PAIR = !ONE;
+    constexpr bool PREFETCH = QS_ADJ_PREFETCH && !ONE;
     static_assert(TB == 9, "exchange2 assumes 512-thread tiles");
-    __shared__ V lds[2 << T];  // two tiles: psi and lambda move through LDS together
+    __shared__ V lds[(PAIR ? 2 : 1) << T];
     __shared__ V tab[kTabMax];
     __shared__ double red[kSlots * (NT / 64)];
     const int tid = threadIdx.x;
@@ -62,48 +69,46 @@ __global__ void __launch_bounds__(1 << TB) adjoint_kernel(PassProg pp)
     if constexpr (turnaround) {
         V p[NR];
         int32_t dg[NR];
-#if QS_ADJ_PREFETCH
-        V np[NR];
-        if (tile < pp.ntiles) turn_load<V, T, TB>(pp, tile, p, tid);
-#endif
+        V np[PREFETCH ? NR : 1];
+        if constexpr (PREFETCH)
+            if (tile < pp.ntiles) turn_load<V, T, TB>(pp, tile, p, tid);
         for (; tile < pp.ntiles; tile += G) {
             turn_load_diag<V, T, TB>(pp, tile, dg, tid);
-#if QS_ADJ_PREFETCH
-            if (tile + G < pp.ntiles) turn_load<V, T, TB>(pp, tile + G, np, tid);
-#else
-            turn_load<V, T, TB>(pp, tile, p, tid);
-#endif
-            turn_compute<V, T, TB, MODE>(pp, tile, p, dg, lds, acc, tid);
-#if QS_ADJ_PREFETCH
+            if constexpr (PREFETCH) {
+                if (tile + G < pp.ntiles) turn_load<V, T, TB>(pp, tile + G, np, tid);
+            } else {
+                turn_load<V, T, TB>(pp, tile, p, tid);
+            }
+            turn_compute<V, T, TB, MODE, PAIR>(pp, tile, p, dg, lds, acc, tid);
+            if constexpr (PREFETCH) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) p[r] = np[r];
-#endif
+                for (int r = 0; r < NR; ++r) p[r] = np[r];
+            }
         }
     } else {
         V p[NR], l[NR];
         int32_t dg[NR];
-#if QS_ADJ_PREFETCH
-        V np[NR], nl[NR];
-        if (tile < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
-#endif
+        V np[PREFETCH ? NR : 1], nl[PREFETCH ? NR : 1];
+        if constexpr (PREFETCH)
+            if (tile < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
         for (; tile < pp.ntiles; tile += G) {
             // this tile's diagonal is requested before the next tile's vectors:
             // memory counters retire in order, so the phase step then waits
             // only for these loads
             if (SH >= 0 ? (SH & kShPhase) != 0 : pp.has_phase != 0) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
-#if QS_ADJ_PREFETCH
-            if (tile + G < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile + G, np, nl, tid);
-#else
-            rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
-#endif
-            rev_tile<V, T, TB, MODE, SH>(pp, tile, p, l, dg, lds, tab, acc, tid);
-#if QS_ADJ_PREFETCH
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                p[r] = np[r];
-                l[r] = nl[r];
+            if constexpr (PREFETCH) {
+                if (tile + G < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile + G, np, nl, tid);
+            } else {
+                rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
             }
-#endif
+            rev_tile<V, T, TB, MODE, SH, PAIR>(pp, tile, p, l, dg, lds, tab, acc, tid);
+            if constexpr (PREFETCH) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r) {
+                    p[r] = np[r];
+                    l[r] = nl[r];
+                }
+            }
         }
     }
     block_sum(acc, red, tid, NT);
@@ -119,19 +124,17 @@ int phase_table_levels(int64_t W) { return phase_levels(W); }
 
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
 {
-    // One tile per workgroup: the hardware dispatcher's dynamic assignment of
-    // workgroups to CUs overlaps loads, butterflies and stores across
-    // workgroups better than a persistent loop (measured on MI355X).
+    // Forward passes: one tile per workgroup -- the hardware dispatcher's
+    // dynamic assignment of workgroups to CUs overlaps loads, butterflies and
+    // stores across workgroups better than a persistent loop (measured on
+    // MI355X).  Adjoint kernels: one persistent workgroup per CU.
     (void)prec;
-#if QS_ADJ_PREFETCH
     if (adjoint == 1 || adjoint == 2) {
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess)
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         return (int64_t)cus < ntiles ? (int64_t)cus : ntiles;
     }
-#endif
-    (void)adjoint;
     return ntiles;
 }
 
@@ -193,34 +196,64 @@ void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
     }
 }
 
-template <int MODE, bool TURN, int SH>
+template <int MODE, bool TURN, int SH, bool ONE>
 void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     constexpr int AT = kAdjThreadBits;
     const dim3 g((unsigned)grid), b(1 << AT);
-    if (prec == 0) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, TURN, MODE, SH>), g, b, 0, st, pp);
-    else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, TURN, MODE, SH>), g, b, 0, st, pp);
+    if (prec == 0) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
+    else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
 }
 
-// Reverse shapes with their own instantiation: a plain stage and the first
-// forward pass undone (phase of layer 1, no writes).  The junction keeps the
-// runtime shape: fixed, it needs more than 256 registers and spills.
+// Adjoint kernel variants.  kAdjPersistent: the runtime-shape persistent
+// kernel with prefetch.  The others take one tile per workgroup and fit in
+// 128 registers without prefetch, so two workgroups share a CU: the
+// turnaround (complex64 only: complex128 would spill at 128 registers), a
+// reverse pass of plain stages, and the reverse of the first forward pass
+// (phase of layer 1, no writes).  The reverse junction keeps the persistent
+// kernel (fixed, it needs more than 256 registers and spills).
+// QS_ADJ_ONE_TILE=0 in the environment selects kAdjPersistent everywhere
+// (for comparisons).
+enum { kAdjPersistent, kAdjOneTurn, kAdjOnePlain, kAdjOneFirst };
+
+int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
+{
+    static const int on = [] {
+        const char *v = getenv("QS_ADJ_ONE_TILE");
+        return v && v[0] == '0' ? 0 : 1;
+    }();
+    if (!on || mode == kModeGeneral) return kAdjPersistent;
+    if (turnaround) return prec == 0 ? kAdjOneTurn : kAdjPersistent;
+    switch (shapes_enabled() ? pass_shape(pp) : -1) {
+    case kShPost: return kAdjOnePlain;
+    case kShInit | kShPhase | kShPost: return kAdjOneFirst;
+    default: return kAdjPersistent;
+    }
+}
+
 template <int MODE>
 void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
-    if (turnaround) {
-        launch_adjoint_s<MODE, true, -1>(prec, pp, grid, st);
-        return;
-    }
-    switch (shapes_enabled() ? pass_shape(pp) : -1) {
-    case kShPost: launch_adjoint_s<MODE, false, kShPost>(prec, pp, grid, st); break;
-    case kShInit | kShPhase | kShPost:
-        launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost>(prec, pp, grid, st);
+    switch (adjoint_variant(prec, pp, turnaround, MODE)) {
+    case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true>(prec, pp, grid, st); break;
+    case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true>(prec, pp, grid, st); break;
+    case kAdjOneFirst: launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost, true>(prec, pp, grid, st); break;
+    default:
+        if (turnaround) launch_adjoint_s<MODE, true, -1, false>(prec, pp, grid, st);
+        else launch_adjoint_s<MODE, false, -1, false>(prec, pp, grid, st);
         break;
-    default: launch_adjoint_s<MODE, false, -1>(prec, pp, grid, st); break;
     }
 }
 }  // namespace
+
+// Grid of the kernel that launch_pass / launch_adjoint_pass pick for pp.
+int64_t tile_grid(int prec, int adjoint, const PassProg &pp)
+{
+    if (adjoint == 0) return pass_grid(prec, 0, pp.ntiles);
+    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
+    return adjoint_variant(prec, pp, adjoint == 1, mode) == kAdjPersistent ? pass_grid(prec, adjoint, pp.ntiles)
+                                                                            : pp.ntiles;
+}
 
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
@@ -238,8 +271,8 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;
     default:
-        if (turnaround) launch_adjoint_s<kModeGeneral, true, -1>(prec, pp, grid, st);
-        else launch_adjoint_s<kModeGeneral, false, -1>(prec, pp, grid, st);
+        if (turnaround) launch_adjoint_s<kModeGeneral, true, -1, false>(prec, pp, grid, st);
+        else launch_adjoint_s<kModeGeneral, false, -1, false>(prec, pp, grid, st);
         break;
     }
     return hipGetLastError();

@@ -204,7 +204,7 @@ __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq,
 // factor accumulate Im <lam| X.. |psi> (invariant under the stage applied to
 // both), then apply RX(-theta) to both.  In tangent form both vectors carry
 // 1/cos^j after j factors, so the terms are rescaled by cos^(2j).
-template <int RB, int MODE, typename V, int NR>
+template <int RB, int MODE, bool PAIR, typename V, int NR>
 __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
                                             uint32_t targets, uint32_t pairs, const RxStage &st, int &cur, int tid,
                                             double &gx)
@@ -214,13 +214,13 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
     const double c2 = st.tan ? st.c * st.c : 1.0;
     for (int i = seq.cnt - 1; i >= 0; --i) {
         const int w = seq.s[i];
-        if constexpr (MODE == kModeGeneral) {
-            if (w != cur) {
-                exchange2<RB>(p, l, lds, cur, w, tid);
-                cur = w;
+        if (MODE == kModeGeneral ? w != cur : i < seq.cnt - 1) {
+            if constexpr (PAIR) {
+                exchange2<RB>(p, l, lds, cur, w, tid);  // LDS holds two tiles
+            } else {
+                exchange<RB>(p, lds, cur, w, tid);
+                exchange<RB>(l, lds, cur, w, tid);
             }
-        } else if (i < seq.cnt - 1) {
-            exchange2<RB>(p, l, lds, cur, w, tid);
             cur = w;
         }
         const uint32_t mask = win_singles<RB>(targets, w) & ~done;
@@ -331,7 +331,7 @@ __device__ __forceinline__ void turn_load_diag(const PassProg &pp, int64_t tile,
                           [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
 }
 
-template <typename V, int T, int TB, int MODE = kModeGeneral>
+template <typename V, int T, int TB, int MODE = kModeGeneral, bool PAIR = true>
 __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                              const int32_t (&dg)[TileCfg<V, T, TB>::NR], V *lds,
                                              double (&acc)[kSlots], int tid)
@@ -356,7 +356,7 @@ __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V
         acc[2] += pr * (double)C;
         l[r] = scale_v(p[r], (R)((double)C * 0.1));
     }
-    unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+    unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
                      [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
 }
@@ -403,7 +403,7 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
 // gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
 // first forward pass (init) only accumulates and writes nothing.
-template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1>
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                          V (&l)[TileCfg<V, T, TB>::NR], const int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                          V *lds, const V *tab, double (&acc)[kSlots], int tid)
@@ -424,7 +424,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     int cur = opaque(pp.load_win);
     if (has_post) {
-        unrun_stage<RB, MODE>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
         if (TAN || pp.post.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -451,7 +451,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         acc[1] += -0.2 * (double)gz;
     }
     if (has_pre) {
-        unrun_stage<RB, MODE>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
+        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
         if (TAN || pp.pre.tan) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {

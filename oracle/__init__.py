@@ -13,7 +13,10 @@ Contents (arXiv:2604.26423):
   * the linear ramp (eq. 4) and its midpoint variant, and the map from the
     paper's (gamma_k, beta_k) to gate angles (eqs. 2-3);
   * dense matrix-exponential references of eqs. (1)-(3) for tiny n;
-  * closed forms: two-qubit circuit and single-layer <C> on any complete graph.
+  * closed forms: two-qubit circuit and single-layer <C> on any complete graph;
+  * noise (Sec. II-C): the circuit with explicit Pauli insertions, the
+    trajectory draw rule, and a density-matrix reference of the depolarizing
+    channel for tiny n, with its two-qubit closed form.
 """
 from __future__ import annotations
 
@@ -62,6 +65,11 @@ def lib():
         L.oracle_cost_histogram.argtypes = [ctypes.c_int, _f64p, _i32p, ctypes.c_int64, _u64p]
         L.oracle_adjoint.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p,
                                      ctypes.POINTER(ctypes.c_double), _f64p, _f64p]
+        L.oracle_pauli_circuit.argtypes = [ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p, ctypes.c_int64,
+                                           _i32p, _i32p, _i32p, _f64p]
+        L.oracle_noise_draws.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_int64, _i32p, _i32p, _i32p,
+                                         ctypes.POINTER(ctypes.c_int64)]
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -365,3 +373,110 @@ def gate_counts(n: int, p: int) -> tuple:
 def state_bytes_fp32(n: int) -> int:
     """Memory of an n-qubit complex single-precision state, Sec. II-E: 2^(n+3) B."""
     return 1 << (n + 3)
+
+
+# --------------------------------------------------------------------------
+# Noise (Sec. II-C): depolarizing channel of uniform rate eps after every
+# two-qubit gate.  Trajectories apply one of the 16 two-qubit Paulis
+# (uniformly) after a gate with probability eps; the density-matrix reference
+# applies the channel itself.  Draw rule and Pauli codes: see oracle.c.
+# --------------------------------------------------------------------------
+PAULI_NAMES = "IXYZ"
+
+
+def noise_threshold(eps: float) -> int:
+    """thr = floor(eps * 2^53): a gate errs when (r0 >> 11) < thr."""
+    eps = float(eps)
+    if not 0.0 <= eps <= 1.0:
+        raise ValueError("eps must lie in [0, 1]")
+    return int(np.floor(eps * 2.0 ** 53))
+
+
+def noise_draws(n: int, p: int, eps: float, seed: int, traj: int) -> tuple:
+    """Non-identity errors of one trajectory: (layer, edge, code) arrays in
+    (layer, edge) order."""
+    cap = p * n * (n - 1) // 2
+    lay = np.empty(max(cap, 1), dtype=np.int32)
+    edg = np.empty_like(lay)
+    cod = np.empty_like(lay)
+    cnt = ctypes.c_int64()
+    _check(lib().oracle_noise_draws(n, p, noise_threshold(eps), int(seed), int(traj), cap, lay, edg, cod,
+                                    ctypes.byref(cnt)), "noise_draws")
+    c = cnt.value
+    return lay[:c].copy(), edg[:c].copy(), cod[:c].copy()
+
+
+def pauli_circuit(n: int, w, theta_zz, theta_x, errors) -> np.ndarray:
+    """Final state with Pauli error (layer, edge, code) applied right after
+    that edge's RZZ gate in that layer (gate by gate, Sec. II-E)."""
+    lay, edg, cod = (np.ascontiguousarray(a, dtype=np.int32) for a in errors)
+    tzz = np.ascontiguousarray(theta_zz, dtype=np.float64)
+    tx = np.ascontiguousarray(theta_x, dtype=np.float64)
+    out = np.empty(2 << n, dtype=np.float64)
+    one = np.zeros(1, dtype=np.int32)
+    _check(lib().oracle_pauli_circuit(n, _w(w), len(tzz), tzz, tx, len(lay),
+                                      lay if len(lay) else one, edg if len(edg) else one,
+                                      cod if len(cod) else one, out), "pauli_circuit")
+    return out.view(np.complex128)
+
+
+def noisy_trajectory(n: int, w, theta_zz, theta_x, eps: float, seed: int, traj: int) -> tuple:
+    """(final state, number of non-identity errors) of trajectory traj."""
+    errs = noise_draws(n, len(theta_zz), eps, seed, traj)
+    return pauli_circuit(n, w, theta_zz, theta_x, errs), len(errs[0])
+
+
+def _pauli_1q(code: int) -> np.ndarray:
+    return [np.eye(2), np.array([[0, 1], [1, 0]]), np.array([[0, -1j], [1j, 0]]),
+            np.array([[1, 0], [0, -1]])][code].astype(np.complex128)
+
+
+def _op_on(n: int, ops: dict) -> np.ndarray:
+    """Dense operator with ops[q] on qubit q (bit q of the index), identity elsewhere."""
+    m = np.array([[1.0 + 0j]])
+    for q in reversed(range(n)):
+        m = np.kron(m, ops.get(q, np.eye(2)))
+    return m
+
+
+def density_expect(n: int, w, theta_zz, theta_x, eps: float) -> float:
+    """<C> (units) of the noisy circuit from its density matrix, tiny n.
+
+    Gate by gate in lexicographic order: rho -> U rho U^+ for RZZ(theta w)
+    then rho -> (1 - eps) rho + (eps / 16) sum_P P rho P over the 16 Paulis
+    on the gate's two qubits; each layer ends with RX(theta_x) on every qubit.
+    """
+    if n > 7:
+        raise ValueError("density matrix reference is for n <= 7")
+    dim = 1 << n
+    x = np.arange(dim)
+    z = 1 - 2 * ((x[:, None] >> np.arange(n)[None, :]) & 1)
+    rho = np.full((dim, dim), 1.0 / dim, dtype=np.complex128)
+    wt = np.asarray(w, dtype=np.float64) / 10.0
+    for k in range(len(theta_zz)):
+        e = 0
+        for i in range(n):
+            for j in range(i + 1, n):
+                d = np.exp(-1j * (theta_zz[k] * wt[e] / 2.0) * z[:, i] * z[:, j])
+                rho = d[:, None] * rho * np.conj(d)[None, :]
+                if eps > 0.0:
+                    acc = np.zeros_like(rho)
+                    for c in range(16):
+                        P = _op_on(n, {i: _pauli_1q(c & 3), j: _pauli_1q(c >> 2)})
+                        acc += P @ rho @ P.conj().T
+                    rho = (1.0 - eps) * rho + (eps / 16.0) * acc
+                e += 1
+        c, s = np.cos(theta_x[k] / 2.0), np.sin(theta_x[k] / 2.0)
+        rx = np.array([[c, -1j * s], [-1j * s, c]])
+        M = _op_on(n, {q: rx for q in range(n)})
+        rho = M @ rho @ M.conj().T
+    C = cost_diagonal(n, w).astype(np.float64) / 10.0
+    return float(np.real(np.sum(np.diag(rho) * C)))
+
+
+def k2_noisy_expect(w_units: float, exp_noiseless: float, eps: float, p: int) -> float:
+    """Two qubits, one gate per layer: the channel keeps the state's coherent
+    part with weight (1 - eps) and replaces the rest by I/4, which every later
+    gate and mixer leaves alone, so <C> = (1-eps)^p <C>_0 + (1 - (1-eps)^p) W/2."""
+    keep = (1.0 - eps) ** p
+    return keep * exp_noiseless + (1.0 - keep) * w_units / 2.0

@@ -17,6 +17,9 @@
  *   - Sec. II-B, eq. (5):  approximation ratio uses C(x*) = max_x C(x).
  *   - Sec. II-E:           each gate updates disjoint pairs (one-qubit gate)
  *                          or quadruples (two-qubit gate) of amplitudes.
+ *   - Sec. II-C:           noise as a two-qubit depolarizing channel of uniform
+ *                          rate eps after every two-qubit gate, sampled here as
+ *                          Pauli insertions (quantum trajectories).
  *
  * Angles are passed as gate angles: layer k applies RZZ(theta_zz[k] * w_ij)
  * on every pair (i<j) and then RX(theta_x[k]) on every qubit, with
@@ -542,6 +545,93 @@ int oracle_adjoint(int n, const int32_t *w, int p, const double *tzz, const doub
     free(lam);
     free(diag);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Noisy trajectories (Sec. II-C).  The depolarizing channel of rate eps  */
+/* on the two qubits (a, b) of a gate,                                    */
+/*   rho -> (1 - eps) rho + eps Tr_ab(rho) (x) I_ab / 4                   */
+/*        = (1 - eps) rho + (eps / 16) sum_P P rho P,                     */
+/* P over the 16 two-qubit Paulis, is unravelled into trajectories: after */
+/* each RZZ gate, with probability eps, one of the 16 Paulis drawn        */
+/* uniformly is applied to the state.                                     */
+/*                                                                        */
+/* Draw rule, for trajectory t, layer k (0-based) and edge e (the         */
+/* lexicographic pair index):                                             */
+/*   (r0, r1, r2, r3) = Philox4x64-10(counter = (t, k, e, 1),             */
+/*                                    key = (seed, 0));                   */
+/*   error iff (r0 >> 11) < thr, with thr = floor(eps * 2^53);            */
+/*   Pauli code c = r1 & 15: P_a = c & 3 on the lower qubit a of the      */
+/*   edge, P_b = c >> 2 on the upper qubit b (0 = I, 1 = X, 2 = Y,        */
+/*   3 = Z).  Code 0 is the identity and changes nothing.                 */
+/* ------------------------------------------------------------------ */
+static void apply_pauli(int n, cplx *psi, int q, int code)
+{
+    switch (code) {
+    case 1: apply_1q(n, psi, q, 0.0, 1.0, 1.0, 0.0); break;  /* X */
+    case 2: apply_1q(n, psi, q, 0.0, -I, I, 0.0); break;     /* Y = [[0, -i], [i, 0]] */
+    case 3: apply_1q(n, psi, q, 1.0, 0.0, 0.0, -1.0); break; /* Z */
+    default: break;
+    }
+}
+
+/*
+ * The circuit with explicit Pauli insertions: error t (err_layer[t],
+ * err_edge[t], err_code[t]) is applied right after the RZZ gate of that edge
+ * in that layer, before the next gate.  Several errors on one gate are
+ * applied in list order.  psi_out: 2^n interleaved complex128.
+ */
+int oracle_pauli_circuit(int n, const int32_t *w, int p, const double *tzz, const double *tx, int64_t nerr,
+                         const int32_t *err_layer, const int32_t *err_edge, const int32_t *err_code,
+                         double *psi_out)
+{
+    if (n < 2 || n > 24 || p < 0 || !w || !psi_out || nerr < 0) return 1;
+    if (nerr > 0 && (!err_layer || !err_edge || !err_code)) return 1;
+    cplx *psi = (cplx *)psi_out;
+    prepare_plus(n, psi);
+    for (int k = 0; k < p; k++) {
+        for (int i = 0; i < n; i++)
+            for (int j = i + 1; j < n; j++) {
+                const int64_t e = edge_id(n, i, j);
+                apply_rzz(n, psi, i, j, tzz[k] * ((double)w[e] / 10.0));
+                for (int64_t t = 0; t < nerr; t++)
+                    if (err_layer[t] == k && err_edge[t] == e) {
+                        apply_pauli(n, psi, i, err_code[t] & 3);
+                        apply_pauli(n, psi, j, (err_code[t] >> 2) & 3);
+                    }
+            }
+        apply_mixer(n, psi, tx[k]);
+    }
+    return 0;
+}
+
+/*
+ * The non-identity errors of trajectory traj by the draw rule above, in
+ * (layer, edge) order.  Writes at most cap of them and the total to *count;
+ * returns 4 when the total exceeds cap.
+ */
+int oracle_noise_draws(int n, int p, uint64_t thr, uint64_t seed, uint64_t traj, int64_t cap, int32_t *err_layer,
+                       int32_t *err_edge, int32_t *err_code, int64_t *count)
+{
+    if (n < 2 || p < 0 || cap < 0 || !count) return 1;
+    const int64_t m = n_edges(n);
+    int64_t c = 0;
+    for (int k = 0; k < p; k++)
+        for (int64_t e = 0; e < m; e++) {
+            uint64_t ctr[4] = {traj, (uint64_t)k, (uint64_t)e, 1}, key[2] = {seed, 0}, r[4];
+            oracle_philox4x64_10(ctr, key, r);
+            if ((r[0] >> 11) >= thr) continue;
+            const int code = (int)(r[1] & 15u);
+            if (code == 0) continue;
+            if (c < cap) {
+                err_layer[c] = k;
+                err_edge[c] = (int32_t)e;
+                err_code[c] = code;
+            }
+            c++;
+        }
+    *count = c;
+    return c > cap ? 4 : 0;
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }

@@ -382,3 +382,113 @@ def test_golden_instance_values():
         assert oracle.weight_total(w) == row["w_total_tenths"]
         if row["n"] <= 16:
             assert oracle.cmax_direct(row["n"], w) == row["cmax_tenths"]
+
+
+# ---------------------------------------------------------------- noise (Sec. II-C)
+def _angles(p, d=0.6):
+    return oracle.gate_angles(*oracle.ramp_midpoint(p, d, d))
+
+
+def test_noise_threshold():
+    assert oracle.noise_threshold(0.0) == 0
+    assert oracle.noise_threshold(1.0) == 1 << 53
+    assert oracle.noise_threshold(0.5) == 1 << 52
+    assert oracle.noise_threshold(2.0 ** -53) == 1
+    with pytest.raises(ValueError):
+        oracle.noise_threshold(1.5)
+
+
+def test_noise_free_trajectory_is_the_noiseless_circuit():
+    n = 5
+    w = inst(n, 11)
+    tzz, tx = _angles(3)
+    psi, nerr = oracle.noisy_trajectory(n, w, tzz, tx, 0.0, 3, 17)
+    assert nerr == 0
+    assert np.array_equal(psi, oracle.simulate(n, w, tzz, tx, 0))
+
+
+def test_noise_draw_statistics():
+    """Error rate eps, each of the 16 Paulis equally likely (15 of them non-identity)."""
+    n, p, eps, N = 6, 3, 0.3, 400
+    gates = N * p * n * (n - 1) // 2
+    codes = []
+    for t in range(N):
+        lay, edg, cod = oracle.noise_draws(n, p, eps, 5, t)
+        assert np.all(np.diff(lay * 1000 + edg) > 0)  # (layer, edge) order, one draw per gate
+        assert np.all((cod >= 1) & (cod <= 15))
+        codes.append(cod)
+    cod = np.concatenate(codes)
+    mean = gates * eps * 15 / 16
+    sd = np.sqrt(gates * eps * 15 / 16 * (1 - eps * 15 / 16))
+    assert abs(len(cod) - mean) < 5 * sd
+    counts = np.bincount(cod, minlength=16)[1:]
+    chi2 = float(((counts - len(cod) / 15) ** 2 / (len(cod) / 15)).sum())
+    assert chi2 < 60  # 14 degrees of freedom: P(chi2 > 60) ~ 1e-7
+    # eps = 1: every gate errs
+    lay, edg, cod = oracle.noise_draws(n, p, 1.0, 5, 0)
+    g = p * n * (n - 1) // 2
+    assert abs(len(cod) - g * 15 / 16) < 5 * np.sqrt(g * 15 / 256)
+
+
+def test_pauli_insertion_xx_commutes_with_the_mixer():
+    """X_a X_b after the last gate of the last layer: it commutes with every RX,
+    so the final state is the noiseless one with bits a and b flipped."""
+    n = 6
+    w = inst(n, 12)
+    tzz, tx = _angles(3)
+    g = n * (n - 1) // 2
+    psi = oracle.pauli_circuit(n, w, tzz, tx, ([2], [g - 1], [1 | (1 << 2)]))
+    ref = oracle.simulate(n, w, tzz, tx, 0)
+    x = np.arange(1 << n)
+    assert np.abs(psi - ref[x ^ (3 << (n - 2))]).max() < 1e-13
+
+
+def test_pauli_insertion_y_and_zz_closed_forms():
+    """With an identity mixer (theta_x = 0) in the layer:
+    Y on the lower qubit a of the last edge after its gate: (Y psi)[x] = (x_a ? i : -i) psi[x ^ 2^a];
+    Z_0 Z_1 after the first gate commutes with every later RZZ: a sign (-1)^(x_0 xor x_1)."""
+    n = 5
+    w = inst(n, 13)
+    tzz = np.array([0.7])
+    tx = np.array([0.0])
+    ref = oracle.simulate(n, w, tzz, tx, 0)
+    x = np.arange(1 << n)
+    g = n * (n - 1) // 2
+    a = n - 2
+    psi = oracle.pauli_circuit(n, w, tzz, tx, ([0], [g - 1], [2]))
+    want = np.where((x >> a) & 1, 1j, -1j) * ref[x ^ (1 << a)]
+    assert np.abs(psi - want).max() < 1e-13
+    psi = oracle.pauli_circuit(n, w, tzz, tx, ([0], [0], [3 | (3 << 2)]))
+    want = np.where(((x ^ (x >> 1)) & 1) == 1, -1.0, 1.0) * ref
+    assert np.abs(psi - want).max() < 1e-13
+    # a misplaced error (before its gate instead of after) would differ: X on qubit 0 of edge (0,1)
+    psi = oracle.pauli_circuit(n, w, tzz, tx, ([0], [0], [1]))
+    assert np.abs(psi - ref[x ^ 1]).max() > 1e-3
+
+
+def test_density_matrix_special_cases():
+    n = 4
+    w = inst(n, 14)
+    tzz, tx = _angles(2)
+    pure = oracle.expect(oracle.simulate(n, w, tzz, tx, 0), oracle.cost_diagonal(n, w))[0]
+    assert abs(oracle.density_expect(n, w, tzz, tx, 0.0) - pure) < 1e-12
+    # eps = 1: every qubit is fully depolarized at its last gate of the layer -> I / 2^n
+    assert abs(oracle.density_expect(n, w, tzz, tx, 1.0) - oracle.weight_total(w) / 20.0) < 1e-12
+    w2 = np.array([7], dtype=np.int32)
+    for p in (1, 2, 4):
+        a, b = _angles(p)
+        e0 = oracle.expect(oracle.simulate(2, w2, a, b, 0), oracle.cost_diagonal(2, w2))[0]
+        for eps in (0.05, 0.5):
+            assert abs(oracle.density_expect(2, w2, a, b, eps) - oracle.k2_noisy_expect(0.7, e0, eps, p)) < 1e-12
+
+
+@pytest.mark.parametrize("n,p,eps", [(4, 2, 0.2), (3, 3, 0.05)])
+def test_trajectory_average_matches_density_matrix(n, p, eps):
+    w = inst(n, 15)
+    tzz, tx = _angles(p)
+    diag = oracle.cost_diagonal(n, w)
+    N = 2000
+    es = np.array([oracle.expect(oracle.noisy_trajectory(n, w, tzz, tx, eps, 21, t)[0], diag)[0]
+                   for t in range(N)])
+    dm = oracle.density_expect(n, w, tzz, tx, eps)
+    assert abs(es.mean() - dm) < 5 * es.std() / np.sqrt(N) + 1e-12

@@ -290,6 +290,60 @@ qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double
 /* Release the batch and its device memory. */
 qs_status qs_batch_free(qs_batch b);
 
+/*
+ * Noisy trajectories (arXiv:2604.26423, Sec. II-C): every RZZ gate is followed
+ * by a two-qubit depolarizing channel of rate eps,
+ *   rho -> (1 - eps) rho + eps Tr_ab(rho) (x) I_ab / 4,
+ * unravelled into Pauli insertions.  Trajectory t draws, for layer k
+ * (0-based) and edge e (lexicographic (0,1),(0,2),...):
+ *   (r0, r1, r2, r3) = Philox4x64-10(counter (t, k, e, 1), key (seed, 0));
+ *   the gate errs iff (r0 >> 11) < floor(eps * 2^53), with the Pauli
+ *   code = r1 & 15: code & 3 on the edge's lower qubit, code >> 2 on the upper
+ *   one (0 = I, 1 = X, 2 = Y, 3 = Z; Y = [[0, -i], [i, 0]]); it is applied right
+ *   after that gate.
+ * The average of a per-trajectory quantity over trajectories estimates its
+ * value under the channel.  States of n = 2..QS_NOISE_MAX_QUBITS qubits; one
+ * workgroup runs one trajectory.
+ */
+#define QS_NOISE_MAX_QUBITS 12
+#define QS_NOISE_MAX_LAYERS 4096
+typedef struct qs_noise_s *qs_noise;
+
+/*
+ * Graph of the trajectories: n qubits, w_tenths as in qs_cost_diagonal (host,
+ * n(n-1)/2 values, copied), prec QS_C64 or QS_C128, all work on
+ * hip_stream (NULL: the default stream).  Builds the cost diagonal on the
+ * device.  Errors: QS_ERR_ARG (n outside 2..QS_NOISE_MAX_QUBITS, bad weights
+ * or precision, null pointers), QS_ERR_OOM, QS_ERR_HIP.
+ */
+qs_status qs_noise_create(int n, int prec, const int32_t *w_tenths, void *hip_stream, qs_noise *out);
+
+/* W_t and C(x*) in tenths (both nullable). */
+qs_status qs_noise_info(qs_noise h, int64_t *w_total_tenths, int32_t *cmax_tenths);
+
+/*
+ * Run trajectories traj0 .. traj0 + ntraj - 1 (1 <= ntraj <= 2^31 - 1) of the
+ * p-layer circuit (host angle arrays theta_zz[p], theta_x[p], as in
+ * qs_forward; 1 <= p <= QS_NOISE_MAX_LAYERS) with error rate eps in [0, 1]
+ * and the given seed.  Device outputs, caller-owned, indexed by
+ * trajectory - traj0:
+ *   exp_c   double[ntraj]: <C> / <psi|psi> of the final state, in units;
+ *   norm    double[ntraj] or NULL: <psi|psi> (1 up to rounding);
+ *   nerr    int32_t[ntraj] or NULL: the number of non-identity Paulis drawn;
+ *   states  [ntraj][2^n] complex (float2 for QS_C64, double2 for QS_C128) or
+ *           NULL: the final state vector of each trajectory, global phase
+ *           included (bit q of the index is qubit q).
+ * Asynchronous on the handle's stream: outputs are complete when the stream
+ * is.  Calls on one handle must not overlap (the angle upload is reused).
+ * Errors: QS_ERR_ARG, QS_ERR_HIP.
+ */
+qs_status qs_noise_run(qs_noise h, int p, const double *theta_zz, const double *theta_x, double eps,
+                       uint64_t seed, int64_t traj0, int64_t ntraj, double *exp_c, double *norm, int32_t *nerr,
+                       void *states);
+
+/* Release the handle and its device memory (synchronises its stream). */
+qs_status qs_noise_free(qs_noise h);
+
 typedef enum {
     QS_KIND_PASS = 0,        /* forward tile passes without a cost phase */
     QS_KIND_PASS_PHASE = 1,  /* forward tile passes that also apply a cost phase (same kernel) */

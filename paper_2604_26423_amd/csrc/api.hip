@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -106,6 +107,15 @@ struct qs_state_s {
     DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer;
     bool prof = false;
     std::vector<ProfRec> recs;
+};
+
+struct qs_noise_s {
+    int n = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    int64_t W = 0;
+    int32_t cmax = 0;
+    DevBuf diag, edges, layers;
+    std::vector<double> layers_h;
 };
 
 struct qs_batch_s {
@@ -1223,6 +1233,119 @@ qs_status qs_batch_forward_grad(qs_batch b, const double *theta_zz, const double
     } catch (...) {
         return fail(QS_ERR_OOM, "qs_batch_forward_grad: host allocation failed");
     }
+}
+
+qs_status qs_noise_create(int n, int prec, const int32_t *w_tenths, void *hip_stream, qs_noise *out)
+{
+    try {
+        if (!out) return fail(QS_ERR_ARG, "null output handle pointer");
+        *out = nullptr;
+        if (n < 2 || n > kNoiseMaxQubits) return fail(QS_ERR_ARG, "n = %d outside 2..%d", n, kNoiseMaxQubits);
+        if (prec != QS_C64 && prec != QS_C128) return fail(QS_ERR_ARG, "bad precision %d", prec);
+        std::vector<int32_t> wm;
+        int64_t W = 0;
+        if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
+        const char *where = "qs_noise_create";
+        std::unique_ptr<qs_noise_s> h(new qs_noise_s);
+        h->n = n;
+        h->prec = prec;
+        h->stream = (hipStream_t)hip_stream;
+        const int ne = n * (n - 1) / 2;
+        std::vector<int32_t> edges((size_t)ne);
+        for (int i = 0, e = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j, ++e) edges[(size_t)e] = i | (j << 4) | (w_tenths[e] << 8);
+        HIPCHK(h->diag.ensure(sizeof(int32_t) << n), where);
+        HIPCHK(h->edges.ensure(sizeof(int32_t) * (size_t)ne), where);
+        HIPCHK(hipMemcpyAsync(h->edges.p, edges.data(), sizeof(int32_t) * (size_t)ne, hipMemcpyHostToDevice,
+                              h->stream), where);
+        if (qs_status st = cost_diagonal_impl(n, 0, w_tenths, (int32_t *)h->diag.p, &h->W, &h->cmax, hip_stream))
+            return st;
+        *out = h.release();
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_OOM, "qs_noise_create: host allocation failed");
+    }
+}
+
+qs_status qs_noise_info(qs_noise h, int64_t *w_total_tenths, int32_t *cmax_tenths)
+{
+    if (!h) return fail(QS_ERR_ARG, "null noise handle");
+    if (w_total_tenths) *w_total_tenths = h->W;
+    if (cmax_tenths) *cmax_tenths = h->cmax;
+    return QS_OK;
+}
+
+qs_status qs_noise_run(qs_noise h, int p, const double *theta_zz, const double *theta_x, double eps, uint64_t seed,
+                       int64_t traj0, int64_t ntraj, double *exp_c, double *norm, int32_t *nerr, void *states)
+{
+    try {
+        if (!h) return fail(QS_ERR_ARG, "null noise handle");
+        if (p < 1 || p > QS_NOISE_MAX_LAYERS) return fail(QS_ERR_ARG, "p = %d outside 1..%d", p, QS_NOISE_MAX_LAYERS);
+        if (!theta_zz || !theta_x) return fail(QS_ERR_ARG, "null angle array");
+        for (int k = 0; k < p; ++k)
+            if (!std::isfinite(theta_zz[k]) || !std::isfinite(theta_x[k]))
+                return fail(QS_ERR_ARG, "non-finite angle in layer %d", k);
+        if (!(eps >= 0.0 && eps <= 1.0)) return fail(QS_ERR_ARG, "eps outside [0, 1]");
+        if (ntraj < 1 || ntraj > 0x7fffffff) return fail(QS_ERR_ARG, "ntraj = %lld outside 1..2^31-1", (long long)ntraj);
+        if (traj0 < 0) return fail(QS_ERR_ARG, "negative first trajectory");
+        if (!exp_c) return fail(QS_ERR_ARG, "null exp_c buffer");
+        if (!aligned(exp_c, 8) || (norm && !aligned(norm, 8)) || (nerr && !aligned(nerr, 4)) ||
+            (states && !aligned(states, h->prec ? 16 : 8)))
+            return fail(QS_ERR_ARG, "misaligned output buffer");
+        const char *where = "qs_noise_run";
+        // per layer: theta_zz, then the mixer in tangent form (u = tan(theta/2), factor cos^n) when every
+        // layer has |cos(theta_x / 2)| >= 1/2, else directly (cos, sin; factor 1)
+        bool tangent = true;
+        for (int k = 0; k < p; ++k) tangent = tangent && std::fabs(std::cos(0.5 * theta_x[k])) >= 0.5;
+        // the previous run may still be reading the uploaded table
+        HIPCHK(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize(), where);
+        h->layers_h.assign((size_t)4 * p, 0.0);
+        for (int k = 0; k < p; ++k) {
+            double *L = &h->layers_h[(size_t)4 * k];
+            const double c = std::cos(0.5 * theta_x[k]), sn = std::sin(0.5 * theta_x[k]);
+            L[0] = theta_zz[k];
+            if (tangent) {
+                L[1] = sn / c;
+                L[3] = std::pow(c, h->n);
+            } else {
+                L[1] = c;
+                L[2] = sn;
+                L[3] = 1.0;
+            }
+        }
+        HIPCHK(h->layers.ensure(sizeof(double) * h->layers_h.size()), where);
+        HIPCHK(hipMemcpyAsync(h->layers.p, h->layers_h.data(), sizeof(double) * h->layers_h.size(),
+                              hipMemcpyHostToDevice, h->stream), where);
+        NoiseProg np{};
+        np.diag = (const int32_t *)h->diag.p;
+        np.edges = (const int32_t *)h->edges.p;
+        np.layers = (const double *)h->layers.p;
+        np.exp_c = exp_c;
+        np.norm = norm;
+        np.nerr = nerr;
+        np.states = states;
+        np.traj0 = (uint64_t)traj0;
+        np.seed = seed;
+        np.thr = (uint64_t)std::floor(eps * 9007199254740992.0);  // eps * 2^53
+        np.W = h->W;
+        np.n = h->n;
+        np.p = p;
+        np.levels = phase_table_levels(3 * h->W);
+        np.amp0 = std::sqrt(std::ldexp(1.0, -h->n));
+        HIPCHK(launch_noise(h->prec, tangent ? 1 : 0, np, ntraj, h->stream), where);
+        return QS_OK;
+    } catch (...) {
+        return fail(QS_ERR_OOM, "qs_noise_run: host allocation failed");
+    }
+}
+
+qs_status qs_noise_free(qs_noise h)
+{
+    if (!h) return QS_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    delete h;
+    return QS_OK;
 }
 
 }  // extern "C"

@@ -224,6 +224,27 @@ struct SmallProg {
 hipError_t launch_small_forward(int prec, const SmallProg &sp, hipStream_t st);
 hipError_t launch_small_adjoint(int prec, const SmallProg &sp, hipStream_t st);
 
+// ---- noisy trajectories (noise.hip): one workgroup per trajectory ----
+constexpr int kNoiseMaxQubits = 12;
+constexpr int kNoiseChunk = 32;  // layers whose error draws are made together
+
+struct NoiseProg {
+    const int32_t *diag;     // 2^n cut values (tenths)
+    const int32_t *edges;    // per edge: a | b << 4 | w << 8 (a < b, w in tenths)
+    const double *layers;    // per layer: theta_zz, u or cos, 0 or sin, mixer factor
+    double *exp_c;           // [ntraj] normalized <C> in units
+    double *norm;            // [ntraj] or null
+    int32_t *nerr;           // [ntraj] non-identity errors, or null
+    void *states;            // [ntraj][2^n] final states, or null
+    uint64_t traj0, seed, thr;
+    int64_t W;
+    int n, p, levels;
+    double amp0;
+};
+
+int noise_threads(int n);
+hipError_t launch_noise(int prec, int tangent, const NoiseProg &np, int64_t ntraj, hipStream_t st);
+
 // Elementwise and readout kernels.
 // |+>: 2^n stored amplitudes, each 2^(-nq/2) (nq = n, or n + 1 in the
 // complement-symmetric layout).

@@ -326,3 +326,71 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Trajectories:
+    """Noisy LR-QAOA (Sec. II-C): a two-qubit depolarizing channel of rate eps
+    after every RZZ gate, sampled as Pauli-insertion trajectories on the GPU
+    (one workgroup per trajectory, n <= 12).  The mean of the per-trajectory
+    <C> estimates <C> under the channel."""
+
+    def __init__(self, w_tenths, precision: str = "c64", stream=None):
+        import torch
+        self.prec = PRECISIONS[precision]
+        self.n = n_from_edges(len(w_tenths))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = _qs.qs_noise_create(self.n, self.prec, w_tenths, self.stream)
+        self.w_total, self.cmax = _qs.qs_noise_info(self.handle)
+
+    def run(self, theta_zz, theta_x, eps: float, seed: int, ntraj: int, traj0: int = 0, states: bool = False):
+        """Trajectories traj0 .. traj0 + ntraj - 1 -> dict of device tensors:
+        exp_c [ntraj] (units), norm [ntraj], nerr [ntraj] (non-identity Paulis)
+        and, with states=True, the final states [ntraj, 2^n]."""
+        import torch
+        dev = torch.device("cuda")
+        out = {"exp_c": torch.empty(ntraj, dtype=torch.float64, device=dev),
+               "norm": torch.empty(ntraj, dtype=torch.float64, device=dev),
+               "nerr": torch.empty(ntraj, dtype=torch.int32, device=dev)}
+        if states:
+            cdt = torch.complex64 if self.prec == _qs.QS_C64 else torch.complex128
+            out["states"] = torch.empty((ntraj, 1 << self.n), dtype=cdt, device=dev)
+        _qs.qs_noise_run(self.handle, theta_zz, theta_x, eps, seed, traj0, ntraj, out["exp_c"], out["norm"],
+                         out["nerr"], out.get("states"))
+        return out
+
+    def ratio(self, theta_zz, theta_x, eps: float, seed: int, ntraj: int, traj0: int = 0):
+        """(mean r, standard error of the mean) over the trajectories,
+        r = <C> / C(x*) (eq. 5 with exact per-trajectory expectations)."""
+        e = self.run(theta_zz, theta_x, eps, seed, ntraj, traj0)["exp_c"].double().cpu().numpy()
+        r = e / (self.cmax / 10.0)
+        return float(r.mean()), float(r.std(ddof=1) / np.sqrt(len(r))) if len(r) > 1 else 0.0
+
+    def random_ratio(self) -> float:
+        """Approximation ratio of the uniform random sampler: E[C] = W / 2."""
+        return (self.w_total / 2.0) / self.cmax
+
+    def close(self):
+        if self.handle is not None:
+            _qs.qs_noise_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def overlap_ratio(r_noisy, r_ideal: float, r_random: float):
+    """r_ovl = (r_QPU - r_random) / (r_ideal - r_random) (Sec. II-C)."""
+    return (np.asarray(r_noisy, dtype=np.float64) - r_random) / (r_ideal - r_random)
+
+
+def fit_k0(eps_acc, r_ovl) -> float:
+    """Least-squares k0 of r_ovl = 2^(-k0 eps_acc) (Sec. II-C), fitted on
+    log2 r_ovl through the origin over the points with r_ovl > 0."""
+    x = np.asarray(eps_acc, dtype=np.float64)
+    y = np.asarray(r_ovl, dtype=np.float64)
+    keep = y > 0
+    x, ly = x[keep], np.log2(y[keep])
+    return float(-(x @ ly) / (x @ x))

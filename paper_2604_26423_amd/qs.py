@@ -40,8 +40,10 @@ EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free
            "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_layout_index", "qs_get_amplitudes",
            "qs_set_amplitudes", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
-           "qs_batch_free"]
+           "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free"]
 QS_BATCH_MAX_QUBITS = 30
+QS_NOISE_MAX_QUBITS = 12
+QS_NOISE_MAX_LAYERS = 4096
 
 
 class QSCircuit(ctypes.Structure):
@@ -100,6 +102,10 @@ def lib() -> ctypes.CDLL:
         "qs_batch_info": ([vp, i32, _c_i64_p, _c_i32_p, ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
         "qs_batch_forward_grad": ([vp, vp, vp, vp, vp, vp], i32),
         "qs_batch_free": ([vp], i32),
+        "qs_noise_create": ([i32, i32, vp, vp, ctypes.POINTER(vp)], i32),
+        "qs_noise_info": ([vp, _c_i64_p, _c_i32_p], i32),
+        "qs_noise_run": ([vp, i32, vp, vp, dbl, u64, i64, i64, vp, vp, vp, vp], i32),
+        "qs_noise_free": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -359,3 +365,32 @@ def qs_batch_forward_grad(b, theta_zz, theta_x, count: int) -> tuple:
 
 def qs_batch_free(b) -> None:
     _check(lib().qs_batch_free(b))
+
+
+def qs_noise_create(n: int, prec: int, w_tenths, stream=None) -> ctypes.c_void_p:
+    w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
+    h = ctypes.c_void_p()
+    _check(lib().qs_noise_create(int(n), int(prec), w.ctypes.data if w.size else None, _stream(stream),
+                                 ctypes.byref(h)))
+    return h
+
+
+def qs_noise_info(h) -> tuple:
+    """(W_t, C_max) in tenths."""
+    W, cm = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().qs_noise_info(h, ctypes.byref(W), ctypes.byref(cm)))
+    return int(W.value), int(cm.value)
+
+
+def qs_noise_run(h, theta_zz, theta_x, eps: float, seed: int, traj0: int, ntraj: int, exp_c,
+                 norm=None, nerr=None, states=None) -> None:
+    """Trajectories traj0 .. traj0 + ntraj - 1 into device buffers (torch tensors or addresses)."""
+    tzz, tx = _f64(theta_zz), _f64(theta_x)
+    if tzz.shape != tx.shape:
+        raise ValueError("theta_zz and theta_x must have the same length")
+    _check(lib().qs_noise_run(h, len(tzz), tzz.ctypes.data, tx.ctypes.data, float(eps), int(seed), int(traj0),
+                              int(ntraj), _ptr(exp_c), _ptr(norm), _ptr(nerr), _ptr(states)))
+
+
+def qs_noise_free(h) -> None:
+    _check(lib().qs_noise_free(h))

@@ -200,3 +200,16 @@ def test_batch_schedule(prec):
         rc, msg = qs.qs_batch_plan_check(small[:k], prec)
         assert rc == 0, msg
     assert qs.qs_batch_plan_check([(T, 2, np.ones(T * (T - 1) // 2, dtype=np.int32))], prec)[0] == 2
+
+
+def test_noise_validation():
+    w = np.ones(66, dtype=np.int32)
+    expect_status(qs.QS_ERR_ARG, qs.qs_noise_create, 13, qs.QS_C64, np.ones(78, dtype=np.int32), 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_noise_create, 1, qs.QS_C64, np.ones(0, dtype=np.int32), 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_noise_create, 12, 2, w, 0)
+    bad = w.copy()
+    bad[5] = -1
+    expect_status(qs.QS_ERR_ARG, qs.qs_noise_create, 12, qs.QS_C64, bad, 0)
+    assert qs.lib().qs_noise_create(12, 0, w.ctypes.data, 0, None) == qs.QS_ERR_ARG
+    assert qs.lib().qs_noise_run(None, 1, None, None, 0.1, 1, 0, 1, FAKE, None, None, None) == qs.QS_ERR_ARG
+    assert qs.lib().qs_noise_free(None) == qs.QS_OK

@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6
 KERNEL_SOURCES = ["paper_2604_26423_amd/csrc/pass.hip", "paper_2604_26423_amd/csrc/tiles.h",
                   "paper_2604_26423_amd/csrc/device.h",
                   "paper_2604_26423_amd/csrc/internal.h", "paper_2604_26423_amd/csrc/plan.h"]
@@ -147,6 +148,85 @@ def batch_run(torch, workloads, stream):
     return out
 
 
+def noise_run(torch, workloads, stream, cpu: bool):
+    """Noisy trajectories (Sec. II-C): throughput at n = 12, p = 10, and the
+    overlap study r_ovl = 2^(-k0 eps_acc) over sizes 8, 10, 12 (Fig. 1b)."""
+    import numpy as np
+    from paper_2604_26423_amd import Trajectories, fit_k0, linear_ramp, overlap_ratio, to_gate_angles
+    from paper_2604_26423_amd import qs as Q
+    b = workloads.NOISE_BENCH
+    g, bb = linear_ramp(b.p, b.delta, b.delta, "midpoint")
+    tzz, tx = to_gate_angles(g, bb, "paper")
+    tr = Trajectories(b.weights(), "c64")
+    dev = torch.device("cuda")
+    exp_c = torch.empty(b.ntraj, dtype=torch.float64, device=dev)
+    nerr = torch.empty(b.ntraj, dtype=torch.int32, device=dev)
+    ts = []
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        Q.qs_noise_run(tr.handle, tzz, tx, b.eps, b.seed, 0, b.ntraj, exp_c, None, nerr, None)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    t = float(np.median(ts[1:]))
+    amp_layers = float(b.ntraj) * (1 << b.n) * b.p
+    flops_per = 4 * b.n + 6  # tangent-form RX per qubit (2 complex FMAs) + the phase multiply
+    achieved = amp_layers * flops_per / (t * 1e-3) / 1e12
+    r = exp_c.cpu().numpy() / (tr.cmax / 10.0)
+    ideal = tr.run(tzz, tx, 0.0, b.seed, 1)["exp_c"].cpu().numpy()[0] / (tr.cmax / 10.0)
+    out = {"workload": f"K{b.n} (seed {b.seed}) p={b.p} midpoint ramp D={b.delta}, eps={b.eps} after every "
+                       f"RZZ gate, {b.ntraj} trajectories, complex64",
+           "ms": round(t, 3), "trajectories_per_s": b.ntraj / (t * 1e-3),
+           "amp_layer_per_s": amp_layers / (t * 1e-3),
+           # FP32 FMA issue without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+           # (the published 157.3 TFLOP/s counts packed FP32, which this build does not emit)
+           "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_UNPACKED_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP32_UNPACKED_TFLOPS, 4), "flops_per_amp_layer": flops_per,
+                        "published_fp32_vector_peak": 157.3, "traffic": None},
+           "r_noisy": float(r.mean()), "r_noisy_sem": float(r.std(ddof=1) / np.sqrt(len(r))),
+           "r_ideal": float(ideal), "r_random": tr.random_ratio(),
+           "mean_errors_per_trajectory": float(nerr.double().mean().item())}
+    tr.close()
+    log(f"noise: {b.ntraj} trajectories n={b.n} p={b.p} in {t:.2f} ms "
+        f"({out['amp_layer_per_s']:.3g} amp-layer/s, {achieved:.1f} TFLOP/s)")
+    study = {}
+    for n in workloads.NOISE_STUDY_N:
+        w = workloads.complete_graph_tenths(n, 100 + n)
+        trn = Trajectories(w, "c64")
+        r_rand = trn.random_ratio()
+        xs, ys, rows = [], [], []
+        for p in workloads.NOISE_STUDY_P:
+            g, bb = linear_ramp(p, 0.6, 0.6, "midpoint")
+            a, c = to_gate_angles(g, bb, "paper")
+            r_id = trn.ratio(a, c, 0.0, 1, 1)[0]
+            for eps in workloads.NOISE_STUDY_EPS:
+                rm, se = trn.ratio(a, c, eps, 100 + n, workloads.NOISE_STUDY_TRAJ)
+                ov = float(overlap_ratio(rm, r_id, r_rand))
+                eacc = p * n * (n - 1) / 2 * eps
+                xs.append(eacc)
+                ys.append(ov)
+                rows.append({"p": p, "eps": eps, "eps_acc": eacc, "r": rm, "r_sem": se, "r_ovl": ov})
+        study[str(n)] = {"k0": fit_k0(xs, ys), "r_random": r_rand, "points": rows}
+        trn.close()
+        log(f"noise study n={n}: k0 = {study[str(n)]['k0']:.3f}")
+    out["overlap_study"] = study
+    if cpu:
+        import oracle
+        w = b.weights()
+        k = 4
+        t0 = time.perf_counter()
+        for i in range(k):
+            oracle.noisy_trajectory(b.n, w, tzz, tx, b.eps, b.seed, i)
+        tc = time.perf_counter() - t0
+        out["cpu_oracle"] = {"trajectories_per_s": k / tc, "amp_layer_per_s": k * (1 << b.n) * b.p / tc,
+                             "cores": oracle.num_threads(), "kind": "oracle",
+                             "sample": f"{k} trajectories of the same workload, gate by gate, complex128"}
+    torch.cuda.empty_cache()
+    return out
+
+
 def sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream):
     """Forward and forward+adjoint at n = 30 for each depth of the sweep."""
     rows = []
@@ -194,6 +274,9 @@ def main():
     ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
     ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched forward+adjoint")
+    ap.add_argument("--no-noise", action="store_true", help="skip the noisy-trajectory runs")
+    ap.add_argument("--noise-only", action="store_true",
+                    help="run only the noisy-trajectory section and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the simulator does not shard the state across GPUs "
@@ -209,6 +292,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.noise_only:
+        print(json.dumps({"noise": noise_run(torch, workloads, torch.cuda.current_stream(), not args.no_cpu)}))
+        return
     run = workloads.LARGE
     n, p = args.n, args.p
     w = workloads.complete_graph_tenths(n, run.seed)
@@ -353,6 +439,9 @@ def main():
 
     if not args.no_batch:
         out["batch"] = batch_run(torch, workloads, stream)
+
+    if not args.no_noise:
+        out["noise"] = noise_run(torch, workloads, stream, not args.no_cpu)
 
     if args.sweep30:
         out["sweep30"] = sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream)

@@ -114,7 +114,7 @@ struct qs_noise_s {
     hipStream_t stream = nullptr;
     int64_t W = 0;
     int32_t cmax = 0;
-    DevBuf diag, edges, layers;
+    DevBuf diag, edges, layers, tabs;
     std::vector<double> layers_h;
 };
 
@@ -1295,7 +1295,9 @@ qs_status qs_noise_run(qs_noise h, int p, const double *theta_zz, const double *
         const char *where = "qs_noise_run";
         // per layer: theta_zz, then the mixer in tangent form (u = tan(theta/2), factor cos^n) when every
         // layer has |cos(theta_x / 2)| >= 1/2, else directly (cos, sin; factor 1)
-        bool tangent = true;
+        // (graphs whose phase table needs more than two levels use the direct form)
+        const int levels = std::max(2, phase_table_levels(3 * h->W));
+        bool tangent = levels == 2;
         for (int k = 0; k < p; ++k) tangent = tangent && std::fabs(std::cos(0.5 * theta_x[k])) >= 0.5;
         // the previous run may still be reading the uploaded table
         HIPCHK(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize(), where);
@@ -1316,7 +1318,9 @@ qs_status qs_noise_run(qs_noise h, int p, const double *theta_zz, const double *
         HIPCHK(h->layers.ensure(sizeof(double) * h->layers_h.size()), where);
         HIPCHK(hipMemcpyAsync(h->layers.p, h->layers_h.data(), sizeof(double) * h->layers_h.size(),
                               hipMemcpyHostToDevice, h->stream), where);
+        HIPCHK(h->tabs.ensure((size_t)p * noise_table_entries() * (h->prec ? 16 : 8)), where);
         NoiseProg np{};
+        np.tabs = h->tabs.p;
         np.diag = (const int32_t *)h->diag.p;
         np.edges = (const int32_t *)h->edges.p;
         np.layers = (const double *)h->layers.p;
@@ -1330,7 +1334,7 @@ qs_status qs_noise_run(qs_noise h, int p, const double *theta_zz, const double *
         np.W = h->W;
         np.n = h->n;
         np.p = p;
-        np.levels = phase_table_levels(3 * h->W);
+        np.levels = levels;
         np.amp0 = std::sqrt(std::ldexp(1.0, -h->n));
         HIPCHK(launch_noise(h->prec, tangent ? 1 : 0, np, ntraj, h->stream), where);
         return QS_OK;

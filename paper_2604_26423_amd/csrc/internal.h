@@ -232,6 +232,7 @@ struct NoiseProg {
     const int32_t *diag;     // 2^n cut values (tenths)
     const int32_t *edges;    // per edge: a | b << 4 | w << 8 (a < b, w in tenths)
     const double *layers;    // per layer: theta_zz, u or cos, 0 or sin, mixer factor
+    void *tabs;              // per layer: kTabMax phase-table entries (float2 / double2)
     double *exp_c;           // [ntraj] normalized <C> in units
     double *norm;            // [ntraj] or null
     int32_t *nerr;           // [ntraj] non-identity errors, or null
@@ -243,6 +244,7 @@ struct NoiseProg {
 };
 
 int noise_threads(int n);
+int noise_table_entries();  // phase-table entries per layer
 hipError_t launch_noise(int prec, int tangent, const NoiseProg &np, int64_t ntraj, hipStream_t st);
 
 // Elementwise and readout kernels.

@@ -94,6 +94,14 @@ __device__ __forceinline__ void noise_sum(double (&x)[2], double *red, int tid)
     }
 }
 
+// LDS slot of cut value x: the low 4 bits are XORed with bits 6..9, so that
+// the 64 lanes of a wave reading one register's values -- consecutive x in
+// the layouts whose window holds the high bits, x 16 (or 2^RB) apart in the
+// layout whose window holds the low bits, both XORed with the frame -- hit
+// 64 different banks.
+// The map is linear over XOR: slot(a ^ b) = slot(a) ^ slot(b).
+__host__ __device__ constexpr int dg_slot(uint32_t x) { return (int)(x ^ ((x >> 6) & 15u)); }
+
 struct NoiseShared {
     int nf, wf, ph, cnt;
     uint32_t ex, ez;
@@ -102,7 +110,16 @@ struct NoiseShared {
 // Cost layer with its errors, then the mixer, for layer k.  The state enters
 // in the layout of the first window of this layer's order and leaves in the
 // layout of the last.
-template <typename V, int N, int MODE, bool ASC>
+// LV = 2: two-level phase table (3 W < 2^13, every graph with weights up to
+// 10 tenths at n <= 12); LV = 0: levels read at run time.
+template <typename V, int LV>
+__device__ __forceinline__ V noise_phase(const V *tab, int levels, int u)
+{
+    if constexpr (LV == 2) return cmul(tab[u & 63], tab[64 + ((u >> 6) & 127)]);
+    else return phase_factor(tab, levels, u);
+}
+
+template <typename V, int N, int MODE, int LV, bool ASC>
 __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[NoiseCfg<N>::NR], V *lds,
                                             const int32_t *dg, V *tab, uint8_t *codes, uint32_t *fm, int *fw,
                                             NoiseShared &sh, uint32_t &m, int &phi, int &nerr, double &fprev,
@@ -112,7 +129,6 @@ __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[N
     using R = typename Real<V>::T;
     constexpr int RB = Cfg::RB, NR = Cfg::NR, NT = Cfg::NT, G = Cfg::G, WL = Cfg::WL, NW = Cfg::NW;
     const double *lay = np.layers + 4 * k;
-    const double tzz = lay[0];
 
     // draws of the next chunk of layers (counter-based: any order gives the same codes)
     if (k % kNoiseChunk == 0) {
@@ -130,8 +146,12 @@ __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[N
     }
     __syncthreads();  // codes visible; the previous layer's table and F reads done
 
-    // phase table of this layer: entry(u) = fprev exp(-i theta (2u - 3W) / 20)
-    build_phase_table(tab, np.levels, -tzz, 3 * np.W, fprev, tid, NT);
+    // phase table of this layer (the same for every trajectory, built by noise_table_kernel)
+    {
+        const V *src = reinterpret_cast<const V *>(np.tabs) + (size_t)k * kTabMax;
+        const int ntab = 64 * (np.levels - 1) + 128;
+        for (int i = tid; i < ntab; i += NT) tab[i] = src[i];
+    }
 
     // the layer's errors, moved to its end (one wave, gates in order)
     if (tid < WL) {
@@ -215,15 +235,18 @@ __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[N
             cf[r] += (__popc(y & mk) & 1) ? wk : 0;
         }
     }
+    V f[NR];
+    const int db = dg_slot((uint32_t)xb ^ m);  // per-thread part of the slot; the register part is a constant
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const uint32_t x = (uint32_t)(xb | (r << s0));
-        const int u = u0 - dg[x ^ m] + 2 * cf[r];
-        V f = phase_factor(tab, np.levels, u);
-        const R sg = (__popc(x & ez) & 1) ? R(-1) : R(1);
-        f = V{sg * f.x, sg * f.y};
-        v[r] = cmul(v[r], f);
+    for (int r = 0; r < NR; ++r)
+        f[r] = noise_phase<V, LV>(tab, np.levels, u0 - dg[db ^ dg_slot((uint32_t)r << s0)] + 2 * cf[r]);
+    if (ez != 0) {  // Z components of the layer's errors (rare): signs
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            if (__popc((uint32_t)(xb | (r << s0)) & ez) & 1) f[r] = V{-f[r].x, -f[r].y};
     }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], f[r]);
     phi = (phi + sh.ph + 2 * (__popc(ez & m) & 1)) & 3;
     m ^= ex;
     nerr += sh.cnt;
@@ -241,7 +264,7 @@ __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[N
     fprev = lay[3];
 }
 
-template <typename V, int N, int MODE>
+template <typename V, int N, int MODE, int LV>
 __global__ void __launch_bounds__(NoiseCfg<N>::NT) noise_kernel(NoiseProg np)
 {
     using Cfg = NoiseCfg<N>;
@@ -257,7 +280,7 @@ __global__ void __launch_bounds__(NoiseCfg<N>::NT) noise_kernel(NoiseProg np)
     __shared__ double red[2 * (NT < 64 ? 1 : NT / 64)];
     const int tid = threadIdx.x;
 
-    for (int i = tid; i < (1 << N); i += NT) dg[i] = np.diag[i];
+    for (int i = tid; i < (1 << N); i += NT) dg[dg_slot((uint32_t)i)] = np.diag[i];
     V v[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) v[r] = V{(R)np.amp0, (R)0};
@@ -267,11 +290,11 @@ __global__ void __launch_bounds__(NoiseCfg<N>::NT) noise_kernel(NoiseProg np)
 
     int k = 0;
     for (; k + 1 < np.p; k += 2) {
-        noise_layer<V, N, MODE, true>(np, k, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
-        noise_layer<V, N, MODE, false>(np, k + 1, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
+        noise_layer<V, N, MODE, LV, true>(np, k, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
+        noise_layer<V, N, MODE, LV, false>(np, k + 1, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
     }
     if (k < np.p)
-        noise_layer<V, N, MODE, true>(np, k, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
+        noise_layer<V, N, MODE, LV, true>(np, k, v, lds, dg, tab, codes, fm, fw, sh, m, phi, nerr, fprev, tid);
     const int s = (np.p & 1) ? Cfg::pos(NW - 1) : Cfg::pos(0);
 
     // readout: psi_true[x ^ m] = i^phi fprev psi_stored[x]
@@ -285,7 +308,7 @@ __global__ void __launch_bounds__(NoiseCfg<N>::NT) noise_kernel(NoiseProg np)
         V a = V{fs * v[r].x, fs * v[r].y};
         const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
         acc[0] += pr;
-        acc[1] += pr * (double)dg[x ^ m];
+        acc[1] += pr * (double)dg[dg_slot(x ^ m)];
         if (out) {
             V t = a;
             if (phi & 1) t = V{-a.y, a.x};
@@ -301,13 +324,25 @@ __global__ void __launch_bounds__(NoiseCfg<N>::NT) noise_kernel(NoiseProg np)
     }
 }
 
-template <typename V, int MODE>
+// Phase table of every layer k: entry(u) = f_(k-1) exp(-i theta_zz,k (2u - 3W) / 20),
+// f_(k-1) the tangent-form factor of the previous layer's mixer (1 for k = 0).
+template <typename V>
+__global__ void __launch_bounds__(256) noise_table_kernel(NoiseProg np)
+{
+    const int k = blockIdx.x;
+    const double f = k == 0 ? 1.0 : np.layers[4 * (k - 1) + 3];
+    build_phase_table(reinterpret_cast<V *>(np.tabs) + (size_t)k * kTabMax, np.levels, -np.layers[4 * k],
+                      3 * np.W, f, threadIdx.x, 256);
+}
+
+template <typename V, int MODE, int LV>
 hipError_t launch_noise_v(const NoiseProg &np, int64_t ntraj, hipStream_t st)
 {
+    hipLaunchKernelGGL(noise_table_kernel<V>, dim3(np.p), dim3(256), 0, st, np);
     const dim3 g((unsigned)ntraj);
     switch (np.n) {
 #define QS_NOISE_CASE(NN)                                                                                       \
-    case NN: hipLaunchKernelGGL((noise_kernel<V, NN, MODE>), g, dim3(NoiseCfg<NN>::NT), 0, st, np); break;
+    case NN: hipLaunchKernelGGL((noise_kernel<V, NN, MODE, LV>), g, dim3(NoiseCfg<NN>::NT), 0, st, np); break;
         QS_NOISE_CASE(2)
         QS_NOISE_CASE(3)
         QS_NOISE_CASE(4)
@@ -327,6 +362,8 @@ hipError_t launch_noise_v(const NoiseProg &np, int64_t ntraj, hipStream_t st)
 
 }  // namespace
 
+int noise_table_entries() { return kTabMax; }
+
 int noise_threads(int n)
 {
     return n >= 10 ? 1 << (n - 4) : (n >= 8 ? 64 : 1 << (n - 2));
@@ -335,11 +372,17 @@ int noise_threads(int n)
 hipError_t launch_noise(int prec, int tangent, const NoiseProg &np, int64_t ntraj, hipStream_t st)
 {
     if (np.n < 2 || np.n > kNoiseMaxQubits || ntraj < 1 || ntraj > 0x7fffffff) return hipErrorInvalidValue;
-    if (prec == 0)
-        return tangent ? launch_noise_v<float2, kModeTan>(np, ntraj, st)
-                       : launch_noise_v<float2, kModeGeneral>(np, ntraj, st);
-    return tangent ? launch_noise_v<double2, kModeTan>(np, ntraj, st)
-                   : launch_noise_v<double2, kModeGeneral>(np, ntraj, st);
+    // np.levels is 2 whenever 3 W < 2^13 (the host raises 1 to 2); larger graphs take the
+    // run-time-levels kernel with the direct-form mixer
+    if (np.levels == 2) {
+        if (prec == 0)
+            return tangent ? launch_noise_v<float2, kModeTan, 2>(np, ntraj, st)
+                           : launch_noise_v<float2, kModeGeneral, 2>(np, ntraj, st);
+        return tangent ? launch_noise_v<double2, kModeTan, 2>(np, ntraj, st)
+                       : launch_noise_v<double2, kModeGeneral, 2>(np, ntraj, st);
+    }
+    return prec == 0 ? launch_noise_v<float2, kModeGeneral, 0>(np, ntraj, st)
+                     : launch_noise_v<double2, kModeGeneral, 0>(np, ntraj, st);
 }
 
 }  // namespace qs

@@ -92,3 +92,27 @@ def random_angles(p: int, seed: int, scale: float = 1.0) -> tuple:
     """Arbitrary per-layer gate angles for tests that do not follow a ramp."""
     rng = np.random.default_rng(seed)
     return (rng.uniform(-scale, scale, size=p), rng.uniform(-scale, scale, size=p))
+
+
+# Noise (Sec. II-C, Fig. 1): depolarizing rate eps after every two-qubit gate.
+@dataclass(frozen=True)
+class NoiseRun:
+    name: str
+    n: int
+    seed: int
+    p: int
+    delta: float      # ramp slope, delta_gamma = delta_beta
+    eps: float
+    ntraj: int
+
+    def weights(self) -> np.ndarray:
+        return complete_graph_tenths(self.n, self.seed)
+
+
+# throughput shape: the paper's largest noisy size, 10 layers, many trajectories
+NOISE_BENCH = NoiseRun("K12_p10_eps0.003", n=12, seed=2, p=10, delta=0.6, eps=0.003, ntraj=65536)
+# overlap study (Fig. 1b): sizes 8, 10, 12 (graph seed 100 + n), depths, rates
+NOISE_STUDY_N = (8, 10, 12)
+NOISE_STUDY_P = (3, 5, 10)
+NOISE_STUDY_EPS = (1e-4, 3e-4, 1e-3, 3e-3, 1e-2, 3e-2)
+NOISE_STUDY_TRAJ = 4096

@@ -235,3 +235,59 @@ def test_n33_adjoint():
     ef2, _ = s.forward(tzz, tx)
     assert ef2 == ef
     s.close()
+
+
+def test_n32_symmetric_layout_matches_full_layout():
+    """The complement-symmetric half state against the full layout on the
+    benchmark circuit: <C>, norm and the adjoint gradient."""
+    from paper_2604_26423_amd import Simulator
+    run = workloads.LARGE
+    w = run.weights()
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(run.p, run.delta_gamma, run.delta_beta))
+    say("n=32 full layout forward + adjoint")
+    s = sim(w, "c64")
+    e_full, n_full = s.forward(tzz, tx)
+    ea_full, gzz_full, gx_full = s.adjoint(tzz, tx)
+    release(_LIVE.pop())
+    say("n=32 symmetric layout forward + adjoint")
+    h = Simulator(w, "c64", symmetric=True)
+    _LIVE.append(h)
+    e, nrm = h.forward(tzz, tx)
+    ea, gzz, gx = h.adjoint(tzz, tx)
+    assert h.cmax == GOLDEN[(32, run.seed)]["cmax_tenths"]
+    assert abs(e - e_full) <= 1e-6 * e_full and abs(nrm - n_full) <= 1e-5
+    assert abs(ea - ea_full) <= 1e-6 * ea_full
+    scale = max(np.abs(gzz_full).max(), np.abs(gx_full).max())
+    assert np.abs(gzz - gzz_full).max() <= 1e-4 * scale and np.abs(gx - gx_full).max() <= 1e-4 * scale
+
+
+def test_n35_symmetric_forward_and_100k_shots():
+    """n = 35 complex64 in the half-state layout (2^34 stored amplitudes,
+    128 GiB + 64 GiB diagonal): C(x*) against the exhaustive search, the shots'
+    cut values against the cut function, and their mean against <C>."""
+    from paper_2604_26423_amd import Simulator
+    n, seed, p, shots_n = 35, 3, 3, 100000
+    key = (n, seed)
+    if key not in GOLDEN:
+        pytest.skip("no golden C(x*) for n = 35")
+    w = workloads.complete_graph_tenths(n, seed)
+    say(f"n={n} p={p} c64 symmetric forward, {shots_n} shots")
+    h = Simulator(w, "c64", symmetric=True)
+    _LIVE.append(h)
+    assert h.cmax == GOLDEN[key]["cmax_tenths"] and h.w_total == GOLDEN[key]["w_total_tenths"]
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(p, 0.6, 0.6))
+    e, nrm = h.forward(tzz, tx)
+    assert abs(nrm - 1) < 1e-5 and 0 < e < h.cmax / 10
+    m2 = 0.0
+    for a, d in zip(chunks(h.psi), chunks(h.diag)):
+        m2 += float(((a.abs() ** 2).to(torch.float64) * (d.to(torch.float64) / 10) ** 2).sum())
+    var = 2 * m2 / nrm - e * e  # the stored half holds half of the probability
+    shots = h.sample(shots_n, seed)
+    assert shots.shape == (shots_n,) and int(shots.max()) < (1 << n)
+    cuts = oracle.cut_values(n, w, shots) / 10.0
+    z = (cuts.mean() - e) / np.sqrt(var / shots_n)
+    say(f"  <C> {e:.6f}, shots mean {cuts.mean():.6f}, z = {z:.2f}")
+    assert abs(z) < 5
+    for q in range(n):
+        bits = (shots >> np.uint64(q)) & np.uint64(1)
+        assert 0 < int(bits.sum()) < shots_n

@@ -11,11 +11,14 @@ measured inside every timed step with HIP events on the library's stream.
 Also reported: the same forward in complex128, the forward+adjoint / forward
 time ratio, HBM bandwidth of the dominant kernel against the 8 TB/s peak,
 and the CPU oracle timed on the host (a bounded sample, see cpu_baseline).
+Side runs in the same line (not part of the headline value): the exact
+cut-value histogram of the final state, the complement-symmetric half-state
+layout, the 512-circuit batched forward+adjoint, the depolarizing-noise
+trajectories (K_12, p = 10, and the overlap study of Sec. II-C), and the
+30-qubit depth sweep (K_30, seed 5, p = 3, 6, 10, 50, 100).
 
-With --sweep30 the line also carries the 30-qubit depth sweep (K_30, seed 5,
-p = 3, 6, 10, 50, 100): forward and forward+adjoint times and r per depth.
-
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c128] [--sweep30]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c128] [--no-sym]
+                       [--no-batch] [--no-noise] [--no-sweep30] [--noise-only]
 """
 import argparse
 import json
@@ -271,7 +274,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c128", action="store_true", help="skip the complex128 comparison")
     ap.add_argument("--cpu-n", type=int, default=27, help="qubits of the CPU oracle sample")
-    ap.add_argument("--sweep30", action="store_true", help="add the 30-qubit depth sweep")
+    ap.add_argument("--no-sweep30", action="store_true", help="skip the 30-qubit depth sweep")
     ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched forward+adjoint")
     ap.add_argument("--no-noise", action="store_true", help="skip the noisy-trajectory runs")
@@ -427,6 +430,26 @@ def main():
                        "exp_c": e128, "c64_exp_c_rel_err": abs(res["exp_c"] - e128) / e128}
 
     # the literal reading of the gate angles (same kernels, other angles)
+    # exact cut-value distribution of the final state (one pass over psi and C)
+    sim.forward(tzz, tx)
+    nb = int(res["w_total"]) + 1
+    hist = torch.empty(nb, dtype=torch.int64, device="cuda")
+    th = []
+    for _ in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        Q.qs_cost_histogram(sim.handle, sim.diag, nb, hist)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        th.append(e0.elapsed_time(e1))
+    t_h = float(np.median(th[1:]))
+    mass = hist.cpu().numpy().view(np.uint64).astype(np.float64) / 2.0 ** 62
+    out["histogram"] = {"ms": round(t_h, 3), "bins": nb, "gbs": round(dim * 12 / (t_h * 1e-3) / 1e9, 1),
+                        "total_probability": float(mass.sum()),
+                        "exp_c_from_histogram": float((mass * np.arange(nb)).sum() / mass.sum() / 10)}
+    log(f"histogram: {nb} bins in {t_h:.2f} ms")
+
     tzz_l, tx_l = to_gate_angles(g, b, "literal")
     e_lit, _ = sim.forward(tzz_l, tx_l)
     out["results"]["r_exact_literal_convention"] = e_lit / (res["cmax"] / 10)
@@ -443,7 +466,7 @@ def main():
     if not args.no_noise:
         out["noise"] = noise_run(torch, workloads, stream, not args.no_cpu)
 
-    if args.sweep30:
+    if not args.no_sweep30:
         out["sweep30"] = sweep30(torch, workloads, Simulator, linear_ramp, to_gate_angles, stream)
 
     if not args.no_cpu:

@@ -104,8 +104,11 @@ def symmetric_run(torch, Simulator, w, tzz, tx, exp_c_full, stream):
         ta.append(e1.elapsed_time(e2))
     t_fwd, t_adj = float(sorted(tf[1:])[1]), float(sorted(ta[1:])[1])
     log(f"symmetric layout: forward {t_fwd:.1f} ms, forward+adjoint {t_adj:.1f} ms")
+    # algorithmic bytes of the half state: read C and psi, write psi per layer (layer 1 skips the read)
+    alg = 2.0 ** (n - 1) * (p * 20 - 8)
     out = {"forward_ms": round(t_fwd, 3), "forward_plus_adjoint_ms": round(t_adj, 3),
            "amp_layer_per_s": 2.0 ** n * p / (t_fwd * 1e-3),
+           "forward_useful_hbm_frac": round(alg / (t_fwd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "state_gib": 2.0 ** (n - 1) * 8 / 2 ** 30,
            "exp_c_rel_diff_vs_full_layout": abs(e - exp_c_full) / exp_c_full}
     sim.close()
@@ -114,7 +117,7 @@ def symmetric_run(torch, Simulator, w, tzz, tx, exp_c_full, stream):
     return out
 
 
-def batch_run(torch, workloads, stream):
+def batch_run(torch, workloads, stream, cpu: bool):
     """512 uneven circuits (n = 14..22, p in {3, 5, 10}): forward + adjoint
     gradient of all of them in one persistent launch."""
     import numpy as np
@@ -148,6 +151,17 @@ def batch_run(torch, workloads, stream):
     bt.close()
     del bt
     torch.cuda.empty_cache()
+    if cpu:
+        import oracle
+        k = 3
+        t0 = time.perf_counter()
+        for it, (a, c) in zip(items[:k], ang[:k]):
+            oracle.adjoint(it.n, it.weights(), a, c)
+        tc = time.perf_counter() - t0
+        out["cpu_oracle"] = {"circuits_per_s": k / tc, "cores": oracle.num_threads(), "kind": "oracle",
+                             "sample": f"the first {k} circuits of the batch (n = "
+                                       f"{', '.join(str(it.n) for it in items[:k])}), gate-by-gate adjoint, "
+                                       f"complex128, {tc:.1f} s"}
     return out
 
 
@@ -445,7 +459,10 @@ def main():
         th.append(e0.elapsed_time(e1))
     t_h = float(np.median(th[1:]))
     mass = hist.cpu().numpy().view(np.uint64).astype(np.float64) / 2.0 ** 62
-    out["histogram"] = {"ms": round(t_h, 3), "bins": nb, "gbs": round(dim * 12 / (t_h * 1e-3) / 1e9, 1),
+    hgbs = dim * 12 / (t_h * 1e-3) / 1e9  # algorithmic: read psi (8 B) and C (4 B) per amplitude
+    out["histogram"] = {"ms": round(t_h, 3), "bins": nb, "gbs": round(hgbs, 1),
+                        "roofline": {"bound": "hbm", "achieved": round(hgbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(hgbs / HBM_PEAK_GBS, 4), "traffic": None},
                         "total_probability": float(mass.sum()),
                         "exp_c_from_histogram": float((mass * np.arange(nb)).sum() / mass.sum() / 10)}
     log(f"histogram: {nb} bins in {t_h:.2f} ms")
@@ -461,7 +478,7 @@ def main():
         out["symmetric"] = symmetric_run(torch, Simulator, w, tzz, tx, res["exp_c"], stream)
 
     if not args.no_batch:
-        out["batch"] = batch_run(torch, workloads, stream)
+        out["batch"] = batch_run(torch, workloads, stream, not args.no_cpu)
 
     if not args.no_noise:
         out["noise"] = noise_run(torch, workloads, stream, not args.no_cpu)
@@ -475,7 +492,7 @@ def main():
         wc = workloads.complete_graph_tenths(nc, run.seed)
         log(f"cpu baseline: oracle, gate-by-gate complex128, n={nc} p={p} on {oracle.num_threads()} threads")
         t0 = time.perf_counter()
-        oracle.simulate(nc, wc, tzz, tx, mode=0)
+        psi_c = oracle.simulate(nc, wc, tzz, tx, mode=0)
         tc = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": 2.0 ** nc * p / tc, "unit": "amp-layer updates/s",
                                "cores": oracle.num_threads(), "kind": "oracle",
@@ -483,6 +500,14 @@ def main():
                                          f"(n(n-1)/2 RZZ + n RX passes per layer), complex128, {tc:.1f} s",
                                "seconds": round(tc, 2)}
         log(f"cpu baseline: {tc:.1f} s")
+        if "histogram" in out:
+            dg = oracle.cost_diagonal(nc, wc)
+            t0 = time.perf_counter()
+            oracle.cost_histogram(psi_c, dg, int(dg.max()) + 1)
+            th = time.perf_counter() - t0
+            out["histogram"]["cpu_oracle"] = {"amplitudes_per_s": 2.0 ** nc / th, "kind": "oracle",
+                                              "sample": f"K{nc} final state of the CPU baseline, {th:.2f} s"}
+        del psi_c
 
     print(json.dumps(out))
 

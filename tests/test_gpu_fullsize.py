@@ -291,3 +291,23 @@ def test_n35_symmetric_forward_and_100k_shots():
     for q in range(n):
         bits = (shots >> np.uint64(q)) & np.uint64(1)
         assert 0 < int(bits.sum()) < shots_n
+
+
+def test_largest_complex128_states_single_layer_closed_form():
+    """The largest complex128 states: n = 33 in the full layout (128 GiB +
+    32 GiB diagonal) and n = 34 in the half-state layout (128 GiB + 64 GiB),
+    one layer against the closed form of <C>, and C(x*) against the golden
+    exhaustive search."""
+    from paper_2604_26423_amd import Simulator
+    a, b = 0.29, -0.53
+    for n, seed, sym in ((33, 3, False), (34, 3, True)):
+        w = workloads.complete_graph_tenths(n, seed)
+        say(f"n={n} c128 {'half-state' if sym else 'full'} layout, one layer")
+        s = Simulator(w, "c128", symmetric=sym)
+        _LIVE.append(s)
+        assert s.cmax == GOLDEN[(n, seed)]["cmax_tenths"]
+        e, nrm = s.forward([a], [b])
+        ref = oracle.p1_expect(n, w, a, b)
+        say(f"  <C> {e:.12f} vs closed form {ref:.12f}, norm - 1 = {nrm - 1:.2e}")
+        assert abs(nrm - 1) <= 1e-12 and abs(e - ref) <= 1e-10 * ref
+        release(_LIVE.pop())

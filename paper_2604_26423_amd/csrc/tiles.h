@@ -72,6 +72,41 @@ __device__ __forceinline__ V phase_factor(const V *tab, int levels, int32_t C)
 template <typename V>
 __device__ __forceinline__ V conj_v(V a) { return V{a.x, -a.y}; }
 
+// Phase factors of a thread's NR amplitudes, level by level.  The loop over
+// levels is uniform and each level's table reads for all registers issue
+// together (a per-amplitude loop over levels would branch and wait once per
+// amplitude).
+template <typename V, int NR>
+__device__ __forceinline__ void phase_factors(const V *tab, int levels, const int32_t (&C)[NR], V (&f)[NR])
+{
+    const uint32_t m0 = levels == 1 ? 127u : 63u;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) f[r] = tab[(uint32_t)C[r] & m0];
+    for (int j = 1; j < levels; ++j) {
+        const uint32_t mj = j == levels - 1 ? 127u : 63u;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) f[r] = cmul(f[r], tab[64 * j + (((uint32_t)C[r] >> (6 * j)) & mj)]);
+    }
+}
+
+// v[r] *= (conjugated, when CONJ) phase factor of C[r], level by level without
+// a factor array (for kernels that keep two vectors in registers).
+template <bool CONJ, typename V, int NR>
+__device__ __forceinline__ void apply_phase_levels(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
+                                                   V (&b)[NR])
+{
+    for (int j = 0; j < levels; ++j) {
+        const uint32_t mj = j == levels - 1 ? 127u : 63u;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            V t = tab[64 * j + (((uint32_t)C[r] >> (6 * j)) & mj)];
+            if constexpr (CONJ) t = conj_v(t);
+            a[r] = cmul(a[r], t);
+            b[r] = cmul(b[r], t);
+        }
+    }
+}
+
 // Hide a uniform value from loop-invariant code motion: without this the
 // compiler keeps every per-register offset of the persistent loop live in
 // scalar registers for the whole kernel and spills them.
@@ -281,9 +316,10 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     }
     if (has_pre) run_stage<RB, MODE>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
     if (has_phase) {
-        const int levels = pp.phase_levels;
+        V f[NR];
+        phase_factors(tab, pp.phase_levels, dg, f);
 #pragma unroll
-        for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], phase_factor<V>(tab, levels, dg[r]));
+        for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], f[r]);
     }
     if (has_post) run_stage<RB, MODE>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     // tangent-form factor of a pass without a phase table (scaling by 1 when
@@ -434,21 +470,15 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (has_phase) {
-        const int levels = pp.phase_levels;
         R gz = 0;  // sum of C Im(conj(l) p) over the thread's amplitudes
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            const int32_t C = dg[r];
             R im = l[r].x * p[r].y;
             im = fma(-l[r].y, p[r].x, im);
-            gz = fma((R)C, im, gz);
-            if (!init) {
-                const V f = conj_v(phase_factor<V>(tab, levels, C));
-                p[r] = cmul(p[r], f);
-                l[r] = cmul(l[r], f);
-            }
+            gz = fma((R)dg[r], im, gz);
         }
         acc[1] += -0.2 * (double)gz;
+        if (!init) apply_phase_levels<true>(tab, pp.phase_levels, dg, p, l);
     }
     if (has_pre) {
         unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);

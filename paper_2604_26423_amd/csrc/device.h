@@ -359,19 +359,47 @@ __device__ __forceinline__ V scale_v(V a, typename Real<V>::T f)
     return V{a.x * f, a.y * f};
 }
 
+// LDS byte offset of slot (thread part) XOR slot (register part).  The slot
+// map is linear over XOR, so the address of register r in a layout is the
+// thread's part XOR a part that depends only on r and the (uniform) window:
+// computed on the scalar unit, it costs one vector XOR per access.  (Left to
+// itself the compiler rebuilds the whole index per register, about six vector
+// instructions.)
+template <typename V>
+__device__ __forceinline__ V &lds_at(V *lds, int byte_off)
+{
+    return *reinterpret_cast<V *>(reinterpret_cast<char *>(lds) + byte_off);
+}
+
+template <int RB, typename V>
+__device__ __forceinline__ int lds_reg_bytes(int r, int win)
+{
+    return __builtin_amdgcn_readfirstlane(lds_slot<RB>(r << win) * (int)sizeof(V));
+}
+
+// Byte offset of the thread's part of a layout, kept opaque so that the
+// compiler XORs it with the register part instead of rebuilding it.
+template <int RB, typename V>
+__device__ __forceinline__ int lds_thread_bytes(int tid, int win)
+{
+    int t = lds_slot<RB>(win_elem(0, tid, win, RB)) * (int)sizeof(V);
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Move the NR amplitudes of every thread from layout `from` to layout `to`
 // through LDS.  Leading barrier: earlier LDS reads of this buffer are done.
 template <int RB, typename V, int NR>
 __device__ __forceinline__ void exchange(V (&v)[NR], V *lds, int from, int to, int tid)
 {
-    const int tf = lds_slot<RB>(win_elem(0, tid, from, RB));
-    const int tt = lds_slot<RB>(win_elem(0, tid, to, RB));
+    const int tf = lds_thread_bytes<RB, V>(tid, from);
+    const int tt = lds_thread_bytes<RB, V>(tid, to);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) lds[tf ^ lds_slot<RB>(r << from)] = v[r];
+    for (int r = 0; r < NR; ++r) lds_at(lds, tf ^ lds_reg_bytes<RB, V>(r, from)) = v[r];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < NR; ++r) v[r] = lds[tt ^ lds_slot<RB>(r << to)];
+    for (int r = 0; r < NR; ++r) v[r] = lds_at(lds, tt ^ lds_reg_bytes<RB, V>(r, to));
 }
 
 // The same move for two arrays at once through an LDS buffer of two tiles:
@@ -380,21 +408,22 @@ template <int RB, typename V, int NR>
 __device__ __forceinline__ void exchange2(V (&a)[NR], V (&b)[NR], V *lds, int from, int to, int tid)
 {
     constexpr int TILE = NR << 9;  // 2^(RB + 9): tiles of the 512-thread kernels
-    const int tf = lds_slot<RB>(win_elem(0, tid, from, RB));
-    const int tt = lds_slot<RB>(win_elem(0, tid, to, RB));
+    V *ldb = lds + TILE;
+    const int tf = lds_thread_bytes<RB, V>(tid, from);
+    const int tt = lds_thread_bytes<RB, V>(tid, to);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int o = tf ^ lds_slot<RB>(r << from);
-        lds[o] = a[r];
-        lds[TILE + o] = b[r];
+        const int o = tf ^ lds_reg_bytes<RB, V>(r, from);
+        lds_at(lds, o) = a[r];
+        lds_at(ldb, o) = b[r];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-        const int o = tt ^ lds_slot<RB>(r << to);
-        a[r] = lds[o];
-        b[r] = lds[TILE + o];
+        const int o = tt ^ lds_reg_bytes<RB, V>(r, to);
+        a[r] = lds_at(lds, o);
+        b[r] = lds_at(ldb, o);
     }
 }
 

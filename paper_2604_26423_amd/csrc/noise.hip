@@ -107,9 +107,6 @@ struct NoiseShared {
     uint32_t ex, ez;
 };
 
-// Cost layer with its errors, then the mixer, for layer k.  The state enters
-// in the layout of the first window of this layer's order and leaves in the
-// layout of the last.
 // LV = 2: two-level phase table (3 W < 2^13, every graph with weights up to
 // 10 tenths at n <= 12); LV = 0: levels read at run time.
 template <typename V, int LV>
@@ -119,6 +116,9 @@ __device__ __forceinline__ V noise_phase(const V *tab, int levels, int u)
     else return phase_factor(tab, levels, u);
 }
 
+// Cost layer with its errors, then the mixer, for layer k.  The state enters
+// in the layout of the first window of this layer's order and leaves in the
+// layout of the last.
 template <typename V, int N, int MODE, int LV, bool ASC>
 __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[NoiseCfg<N>::NR], V *lds,
                                             const int32_t *dg, V *tab, uint8_t *codes, uint32_t *fm, int *fw,

@@ -54,13 +54,6 @@ __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t k0)
     return w0;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Inclusive scan across the 64 lanes of a wave.
 __device__ __forceinline__ uint64_t wave_scan_u64(uint64_t v, int lane)
 {
@@ -72,29 +65,57 @@ __device__ __forceinline__ uint64_t wave_scan_u64(uint64_t v, int lane)
     return v;
 }
 
-// Pass A: one workgroup per block of 8192 amplitudes.
+// Two consecutive amplitudes (an even index): one 16-byte load for complex64.
+template <typename V> struct AmpPair;
+template <> struct AmpPair<float2> {
+    static __device__ __forceinline__ void load(const float2 *p, float2 &a, float2 &b)
+    {
+        const float4 t = *reinterpret_cast<const float4 *>(p);
+        a = float2{t.x, t.y};
+        b = float2{t.z, t.w};
+    }
+};
+template <> struct AmpPair<double2> {
+    static __device__ __forceinline__ void load(const double2 *p, double2 &a, double2 &b)
+    {
+        a = p[0];
+        b = p[1];
+    }
+};
+
+// Pass A: one workgroup per block of 8192 amplitudes.  Thread t reads the
+// pairs (i 512 + 2 t, +1), i = 0..15, all issued before any arithmetic; the 32
+// lanes of half a wave then hold one 64-amplitude sub-block and sum it with
+// five shuffles.
 template <typename V>
 __global__ void __launch_bounds__(256) sample_blocks_kernel(const V *psi, uint64_t *sub, uint64_t *blk,
                                                             int32_t *flag)
 {
+    constexpr int NL = (1 << kBlockBits) / 512;  // pairs per thread
     __shared__ uint64_t ssum[kSubPerBlock];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t b = blockIdx.x;
     const V *blkp = psi + (b << kBlockBits);
-    const int fb = (int)(swz_fold(b) << kSwzDst);  // layout of the block's entries (internal.h)
-    for (int jj = 0; jj < kSubPerBlock / 4; ++jj) {
-        const int j = wave * (kSubPerBlock / 4) + jj;
-        const uint64_t q = qval_of(blkp[(j * 64 + lane) ^ fb], flag);
-        const uint64_t s = wave_sum_u64(q);
-        if (lane == 0) ssum[j] = s;
+    // layout of the block's entries (internal.h): the fold moves bits 4..12 only,
+    // so a pair at an even index stays a pair
+    const int fb = (int)(swz_fold(b) << kSwzDst);
+    V a[NL], c[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) AmpPair<V>::load(blkp + ((i * 512 + 2 * tid) ^ fb), a[i], c[i]);
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        uint64_t q = qval_of(a[i], flag) + qval_of(c[i], flag);
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) q += __shfl_xor(q, off, 64);
+        if ((lane & 31) == 0) ssum[i * 8 + 2 * wave + (lane >> 5)] = q;
     }
     __syncthreads();
     if (wave == 0) {
-        const uint64_t a = ssum[2 * lane], c = ssum[2 * lane + 1];
-        const uint64_t incl = wave_scan_u64(a + c, lane);
-        const uint64_t excl = incl - (a + c);
+        const uint64_t a0 = ssum[2 * lane], a1 = ssum[2 * lane + 1];
+        const uint64_t incl = wave_scan_u64(a0 + a1, lane);
+        const uint64_t excl = incl - (a0 + a1);
         sub[b * kSubPerBlock + 2 * lane] = excl;
-        sub[b * kSubPerBlock + 2 * lane + 1] = excl + a;
+        sub[b * kSubPerBlock + 2 * lane + 1] = excl + a0;
         if (lane == 63) blk[b] = incl;
     }
 }

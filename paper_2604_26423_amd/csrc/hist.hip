@@ -62,11 +62,7 @@ __global__ void __launch_bounds__(kHT) hist_kernel(const V *__restrict__ psi, co
     const unsigned last = (unsigned)nbins - 1u;
     double acc = 0.0;
     int32_t fl = 0;
-    for (int64_t x = lo + (int64_t)tid * K; x < hi; x += (int64_t)kHT * K) {
-        V a[K];
-        int32_t c[K];
-        Wd::load(psi, x, a);
-        Wd::load_c(diag, x, c);
+    auto add = [&](const V (&a)[K], const int32_t (&c)[K]) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double P = prob_fp64((double)a[k].x, (double)a[k].y);
@@ -75,6 +71,29 @@ __global__ void __launch_bounds__(kHT) hist_kernel(const V *__restrict__ psi, co
             const unsigned b = (unsigned)c[k] > last ? last : (unsigned)c[k];
             if (q) atomicAdd((unsigned long long *)&dst[b], (unsigned long long)q);
         }
+    };
+    // U strides per step, all loads issued before the atomics (per is a
+    // multiple of the stride; the tail loop takes what is left over)
+    constexpr int U = 4;
+    const int64_t S = (int64_t)kHT * K;
+    int64_t x = lo + (int64_t)tid * K;
+    for (; x + (U - 1) * S < hi; x += U * S) {
+        V a[U][K];
+        int32_t c[U][K];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            Wd::load(psi, x + u * S, a[u]);
+            Wd::load_c(diag, x + u * S, c[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) add(a[u], c[u]);
+    }
+    for (; x < hi; x += S) {
+        V a[K];
+        int32_t c[K];
+        Wd::load(psi, x, a);
+        Wd::load_c(diag, x, c);
+        add(a, c);
     }
     if (fl) *flag = fl;
     // fixed-order block sum of the FP64 mass

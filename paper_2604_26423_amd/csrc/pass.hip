@@ -94,14 +94,17 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
         for (; tile < pp.ntiles; tile += G) {
             // this tile's diagonal is requested before the next tile's vectors:
             // memory counters retire in order, so the phase step then waits
-            // only for these loads
-            if (SH >= 0 ? (SH & kShPhase) != 0 : pp.has_phase != 0) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
+            // only for these loads.  The one-tile junction loads it at the
+            // phase point instead (LATE), to stay within 128 registers.
+            constexpr bool LATE = ONE && SH == (kShPre | kShPhase | kShPost);
+            if (!LATE && (SH >= 0 ? (SH & kShPhase) != 0 : pp.has_phase != 0))
+                rev_load_diag<V, T, TB>(pp, tile, dg, tid);
             if constexpr (PREFETCH) {
                 if (tile + G < pp.ntiles) rev_load_vectors<V, T, TB>(pp, tile + G, np, nl, tid);
             } else {
                 rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
             }
-            rev_tile<V, T, TB, MODE, SH, PAIR>(pp, tile, p, l, dg, lds, tab, acc, tid);
+            rev_tile<V, T, TB, MODE, SH, PAIR, LATE>(pp, tile, p, l, dg, lds, tab, acc, tid);
             if constexpr (PREFETCH) {
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -208,13 +211,13 @@ void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st
 // Adjoint kernel variants.  kAdjPersistent: the runtime-shape persistent
 // kernel with prefetch.  The others take one tile per workgroup and fit in
 // 128 registers without prefetch, so two workgroups share a CU: the
-// turnaround (complex64 only: complex128 would spill at 128 registers), a
-// reverse pass of plain stages, and the reverse of the first forward pass
-// (phase of layer 1, no writes).  The reverse junction keeps the persistent
-// kernel (fixed, it needs more than 256 registers and spills).
-// QS_ADJ_ONE_TILE=0 in the environment selects kAdjPersistent everywhere
-// (for comparisons).
-enum { kAdjPersistent, kAdjOneTurn, kAdjOnePlain, kAdjOneFirst };
+// turnaround, a reverse pass of plain stages, the reverse of the first
+// forward pass (phase of layer 1, no writes) and the reverse junction (stage,
+// phase, stage; its diagonal is loaded at the phase point).  The turnaround
+// and the junction are one-tile for complex64 only: in complex128 they spill
+// at 128 registers.  QS_ADJ_ONE_TILE=0 in the environment selects
+// kAdjPersistent everywhere (for comparisons).
+enum { kAdjPersistent, kAdjOneTurn, kAdjOnePlain, kAdjOneFirst, kAdjOneJunc };
 
 int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
 {
@@ -227,6 +230,7 @@ int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
     switch (shapes_enabled() ? pass_shape(pp) : -1) {
     case kShPost: return kAdjOnePlain;
     case kShInit | kShPhase | kShPost: return kAdjOneFirst;
+    case kShPre | kShPhase | kShPost: return prec == 0 ? kAdjOneJunc : kAdjPersistent;
     default: return kAdjPersistent;
     }
 }
@@ -238,6 +242,7 @@ void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid
     case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true>(prec, pp, grid, st); break;
     case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true>(prec, pp, grid, st); break;
     case kAdjOneFirst: launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost, true>(prec, pp, grid, st); break;
+    case kAdjOneJunc: launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true>(prec, pp, grid, st); break;
     default:
         if (turnaround) launch_adjoint_s<MODE, true, -1, false>(prec, pp, grid, st);
         else launch_adjoint_s<MODE, false, -1, false>(prec, pp, grid, st);

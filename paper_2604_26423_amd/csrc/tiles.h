@@ -82,6 +82,7 @@ __device__ __forceinline__ void phase_factors(const V *tab, int levels, const in
     const uint32_t m0 = levels == 1 ? 127u : 63u;
 #pragma unroll
     for (int r = 0; r < NR; ++r) f[r] = tab[(uint32_t)C[r] & m0];
+#pragma unroll 1
     for (int j = 1; j < levels; ++j) {
         const uint32_t mj = j == levels - 1 ? 127u : 63u;
 #pragma unroll
@@ -89,20 +90,26 @@ __device__ __forceinline__ void phase_factors(const V *tab, int levels, const in
     }
 }
 
-// v[r] *= (conjugated, when CONJ) phase factor of C[r], level by level without
-// a factor array (for kernels that keep two vectors in registers).
-template <bool CONJ, typename V, int NR>
-__device__ __forceinline__ void apply_phase_levels(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
-                                                   V (&b)[NR])
+// v[r] *= conj(phase factor of C[r]) for two vectors, half of the registers at
+// a time: the runtime loop over levels carries only the half's factors, not
+// the two vectors.
+template <typename V, int NR>
+__device__ __forceinline__ void unphase_halves(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
+                                               V (&b)[NR])
 {
-    for (int j = 0; j < levels; ++j) {
-        const uint32_t mj = j == levels - 1 ? 127u : 63u;
+    constexpr int H = NR > 1 ? NR / 2 : 1;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            V t = tab[64 * j + (((uint32_t)C[r] >> (6 * j)) & mj)];
-            if constexpr (CONJ) t = conj_v(t);
-            a[r] = cmul(a[r], t);
-            b[r] = cmul(b[r], t);
+    for (int h = 0; h < NR; h += H) {
+        int32_t c[H];
+        V f[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) c[i] = C[h + i];
+        phase_factors(tab, levels, c, f);
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const V t = conj_v(f[i]);
+            a[h + i] = cmul(a[h + i], t);
+            b[h + i] = cmul(b[h + i], t);
         }
     }
 }
@@ -438,10 +445,11 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
 // gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
-// first forward pass (init) only accumulates and writes nothing.
-template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true>
+// first forward pass (init) only accumulates and writes nothing.  LATE: dg is
+// loaded here at the phase point rather than by the caller.
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true, bool LATE = false>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
-                                         V (&l)[TileCfg<V, T, TB>::NR], const int32_t (&dg)[TileCfg<V, T, TB>::NR],
+                                         V (&l)[TileCfg<V, T, TB>::NR], int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                          V *lds, const V *tab, double (&acc)[kSlots], int tid)
 {
     using Cfg = TileCfg<V, T, TB>;
@@ -470,6 +478,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (has_phase) {
+        if constexpr (LATE) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
         R gz = 0;  // sum of C Im(conj(l) p) over the thread's amplitudes
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -477,8 +486,11 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
             im = fma(-l[r].y, p[r].x, im);
             gz = fma((R)dg[r], im, gz);
         }
+        // pin the sum here: sunk past the next stage, it would keep the
+        // vectors' values at the phase point live through that stage
+        asm volatile("" : "+v"(gz));
         acc[1] += -0.2 * (double)gz;
-        if (!init) apply_phase_levels<true>(tab, pp.phase_levels, dg, p, l);
+        if (!init) unphase_halves(tab, pp.phase_levels, dg, p, l);
     }
     if (has_pre) {
         unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);

@@ -97,7 +97,7 @@ template <typename V, int NR>
 __device__ __forceinline__ void unphase_halves(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
                                                V (&b)[NR])
 {
-    constexpr int H = NR > 1 ? NR / 2 : 1;
+    constexpr int H = NR >= 4 ? NR / 4 : 1;
 #pragma unroll
     for (int h = 0; h < NR; h += H) {
         int32_t c[H];

@@ -132,14 +132,16 @@ __global__ void __launch_bounds__(1 << TBB) batch_kernel(BatchArgs a)
     }
 }
 
-// One workgroup per step: that step's phase table (forward passes carry the
-// tangent-form factor of their stages; reverse passes use the plain phase).
+// One workgroup per step: that step's phase table.  Forward passes, and
+// reverse passes in tangent form that undo a phase, carry the tangent-form
+// factor of their stages (see rev_tile); the others use the plain phase.
 template <typename V>
 __global__ void __launch_bounds__(256) batch_table_kernel(const BatchStep *steps, V *tabs)
 {
     const BatchStep &st = steps[blockIdx.x];
     if (!st.pp.has_phase || st.tab_off < 0) return;
-    const double f = st.kind == 0 ? st.pp.factor : 1.0;
+    const bool fold = st.kind == 2 && st.mode == kModeTan && !st.pp.init;  // run_item runs kModeTan or general
+    const double f = st.kind == 0 || fold ? st.pp.factor : 1.0;
     build_phase_table(tabs + st.tab_off, st.pp.phase_levels, st.pp.theta_zz, st.pp.W, f, threadIdx.x, 256);
 }
 

@@ -60,7 +60,10 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
     __shared__ double red[kSlots * (NT / 64)];
     const int tid = threadIdx.x;
     if (pp.has_phase) {
-        build_phase_table(tab, pp.phase_levels, pp.theta_zz, pp.W, 1.0, tid, NT);
+        // reverse passes in tangent form fold the stages' factors into the
+        // table (see rev_tile)
+        const bool fold = !turnaround && MODE != kModeGeneral && !pp.init;
+        build_phase_table(tab, pp.phase_levels, pp.theta_zz, pp.W, fold ? pp.factor : 1.0, tid, NT);
         __syncthreads();
     }
     double acc[kSlots] = {0.0, 0.0, 0.0, 0.0};

@@ -467,9 +467,15 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     const Geom gg = geom_of(pp);
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     int cur = opaque(pp.load_win);
+    // In tangent form, when the pass undoes a phase layer, the stages' real
+    // factors fpost * fpre sit in the phase table (one scale per factor
+    // instead of one per amplitude of each vector, see the kernel); the
+    // gradient sums taken on the vectors without fpost (phase point) or with
+    // an extra fpre (pre stage) are corrected by fpost^2 and 1 / fpre^2.
+    const bool fold = TAN && has_phase && !init;
     if (has_post) {
         unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
-        if (TAN || pp.post.tan) {
+        if ((TAN || pp.post.tan) && !fold) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 p[r] = scale_v(p[r], fpost);
@@ -489,12 +495,14 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         // pin the sum here: sunk past the next stage, it would keep the
         // vectors' values at the phase point live through that stage
         asm volatile("" : "+v"(gz));
-        acc[1] += -0.2 * (double)gz;
+        acc[1] += -0.2 * (double)gz * (fold && has_post ? pp.fpost * pp.fpost : 1.0);
         if (!init) unphase_halves(tab, pp.phase_levels, dg, p, l);
     }
     if (has_pre) {
-        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, acc[2]);
-        if (TAN || pp.pre.tan) {
+        double gpre = 0.0;
+        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, gpre);
+        acc[2] += fold ? gpre / (pp.fpre * pp.fpre) : gpre;
+        if ((TAN || pp.pre.tan) && !fold) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 p[r] = scale_v(p[r], fpre);

@@ -240,6 +240,36 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
                           double *d_theta_x);
 
 /*
+ * The same gradient with stored checkpoints instead of uncomputing psi (the
+ * "store" mode of the reverse sweep, for states small enough that the
+ * checkpoints fit; the uncompute mode above needs only two state vectors).
+ * The forward keeps the state after every tile pass but the last two in
+ * ckpt_buf and the one after the second-to-last in the state buffer; each
+ * reverse pass then reads psi from its checkpoint and stores lambda only, so
+ * psi carries no error accumulated by undoing passes.  Same results as
+ * qs_adjoint_grad up to rounding.
+ * ckpt_buf: caller-owned device buffer of ckpt_bytes >= the size that
+ * qs_adjoint_ckpt_bytes reports for p (256-byte aligned, not overlapping
+ * the state or lambda_buf); it may be NULL when that size is 0 (one
+ * workgroup holds the whole state, or the circuit has two tile passes).
+ * The reverse passes do not write the state buffer: on return it holds the
+ * output of the second-to-last forward pass.  Other arguments, errors and
+ * synchronisation as qs_adjoint_grad.
+ */
+qs_status qs_adjoint_grad_store(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                                const double *theta_zz, const double *theta_x, void *ckpt_buf,
+                                size_t ckpt_bytes, void *lambda_buf, size_t lambda_bytes,
+                                double *exp_c, double *d_theta_zz, double *d_theta_x);
+
+/*
+ * Checkpoint bytes qs_adjoint_grad_store needs for p layers on this state:
+ * (P - 2) state sizes for a circuit of P tile passes (P = p (passes per
+ * layer - 1) + 1), 0 when one workgroup holds the state.
+ * Errors: QS_ERR_ARG (p < 1 or p > 2^20, null bytes).
+ */
+qs_status qs_adjoint_ckpt_bytes(qs_state s, int p, size_t *bytes);
+
+/*
  * Per-kernel timing.  While enabled, HIP events bracket every kernel the
  * handle launches.  qs_profile_read synchronises and reports, for one kernel
  * kind, the launch count, the summed event time and the summed algorithmic

@@ -199,6 +199,7 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     PassProg pp{};
     pp.psi = psi;
     pp.lam = nullptr;
+    pp.psi_out = psi;
     pp.diag = cc.diag;
     pp.partials = partials;
     pp.ntiles = (int64_t)1 << (n - T);
@@ -440,7 +441,28 @@ qs_status run_small_adjoint(qs_state s, const Circuit &cc, void *lam, const char
     return QS_OK;
 }
 
-qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *where)
+// Tile passes of the forward circuit for p layers (0 when one workgroup holds
+// the state).
+int64_t forward_pass_count(qs_state s, int p)
+{
+    if (s->n <= tile_bits(s->prec)) return 0;
+    return (int64_t)forward_specs((int)plan_for(s).size(), p).size();
+}
+
+// States a checkpointing adjoint keeps besides the state buffer: the outputs
+// of forward passes 0 .. P-3 (the output of pass P-2 stays in the state
+// buffer, where the turnaround reads it).
+int64_t ckpt_states(qs_state s, int p)
+{
+    const int64_t P = forward_pass_count(s, p);
+    return P > 2 ? P - 2 : 0;
+}
+
+// ckpt == nullptr: uncompute (the reverse passes undo every pass on psi).
+// Otherwise store: the forward writes the output of pass i to checkpoint i
+// (ckpt + i states, the state buffer for i = P-2) and reverse pass i reads
+// psi from checkpoint i and stores lambda only.
+qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *where, void *ckpt = nullptr)
 {
     const int T = tile_bits(s->prec);
     const int nres = 2 + 2 * cc.p;
@@ -455,9 +477,17 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     const double dim = ldexp(1.0, s->n), ab = (double)amp_bytes(s->prec);
     int64_t grid = 0;
 
+    const int P = (int)ks.size();
+    const size_t sb = qs_state_bytes(s->n, s->prec);
+    auto ck = [&](int i) -> void * { return i == P - 2 ? s->psi : (void *)((char *)ckpt + (size_t)i * sb); };
+
     // forward, all but the last pass
-    for (size_t i = 0; i + 1 < ks.size(); ++i) {
+    for (int i = 0; i + 1 < P; ++i) {
         PassProg pp = make_prog(s, geo[ks[i].pass], ks[i], cc, kFwdThreadBits);
+        if (ckpt) {
+            if (i > 0) pp.psi = ck(i - 1);
+            pp.psi_out = ck(i);
+        }
         if (qs_status st = launch_tiles(s, pp, 0, 0, pp.has_phase ? QS_KIND_PASS_PHASE : QS_KIND_PASS,
                                         pass_bytes(s, pp), &grid, where))
             return st;
@@ -478,7 +508,11 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
         PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
         pp.lam = lam;
         pp.load_win = pp.final_win;
-        const double by = dim * ab * (pp.init ? 2.0 : 4.0) + (pp.has_phase ? dim * 4.0 : 0.0);
+        if (ckpt) {
+            pp.psi = ck(i);
+            pp.psi_out = nullptr;
+        }
+        const double by = dim * ab * (pp.init ? 2.0 : ckpt ? 3.0 : 4.0) + (pp.has_phase ? dim * 4.0 : 0.0);
         if (qs_status st = launch_tiles(s, pp, 2, 0, QS_KIND_ADJOINT, by, &grid, where)) return st;
         const int map[kSlots] = {k.post >= 0 ? 2 + cc.p + k.post : -1, k.phase >= 0 ? 2 + k.phase : -1,
                                  k.pre >= 0 ? 2 + cc.p + k.pre : -1, -1};
@@ -1017,9 +1051,16 @@ qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, 
     return QS_OK;
 }
 
-qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
-                          const double *theta_zz, const double *theta_x, void *lambda_buf, size_t lambda_bytes,
-                          double *exp_c, double *d_theta_zz, double *d_theta_x)
+static bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + nb && y < x + na;
+}
+
+static qs_status adjoint_entry(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                               const double *theta_zz, const double *theta_x, void *ckpt_buf, size_t ckpt_bytes,
+                               bool store, void *lambda_buf, size_t lambda_bytes, double *exp_c,
+                               double *d_theta_zz, double *d_theta_x, const char *where)
 {
     try {
         if (qs_status st = check_state(s)) return st;
@@ -1034,14 +1075,29 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
             if (!aligned(lambda_buf, 256)) return fail(QS_ERR_ARG, "lambda buffer must be 256-byte aligned");
             if (lambda_buf == s->psi) return fail(QS_ERR_ARG, "lambda buffer aliases the state");
         }
-        const char *where = "qs_adjoint_grad";
+        void *ckpt = nullptr;
+        if (store) {
+            const size_t cneed = (size_t)ckpt_states(s, p) * need;
+            if (cneed > 0) {
+                if (!ckpt_buf) return fail(QS_ERR_ARG, "null checkpoint buffer (%zu bytes needed)", cneed);
+                if (ckpt_bytes < cneed)
+                    return fail(QS_ERR_ARG, "checkpoint buffer too small: %zu < %zu", ckpt_bytes, cneed);
+                if (!aligned(ckpt_buf, 256)) return fail(QS_ERR_ARG, "checkpoint buffer must be 256-byte aligned");
+                if (overlaps(ckpt_buf, cneed, s->psi, need) ||
+                    (lambda_buf && overlaps(ckpt_buf, cneed, lambda_buf, need)))
+                    return fail(QS_ERR_ARG, "checkpoint buffer overlaps the state or the adjoint vector");
+                ckpt = ckpt_buf;
+            } else if (s->n > tile_bits(s->prec)) {
+                ckpt = s->psi;  // two passes: the one checkpoint is the state buffer
+            }
+        }
         void *lam = lambda_buf;
         if (!lam) {
             HIPCHK(s->lambda.ensure(need), where);
             lam = s->lambda.p;
         }
         Circuit cc{diag_dev, w_total_tenths, p, theta_zz, theta_x};
-        if (qs_status st = run_adjoint(s, cc, lam, where)) return st;
+        if (qs_status st = run_adjoint(s, cc, lam, where, ckpt)) return st;
         std::vector<double> r(2 + 2 * (size_t)p);
         if (qs_status st = read_results(s, r.data(), (int)r.size(), where)) return st;
         if (!lambda_buf) s->lambda.release();
@@ -1053,8 +1109,39 @@ qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_t
         }
         return QS_OK;
     } catch (...) {
-        return fail(QS_ERR_OOM, "qs_adjoint_grad: host allocation failed");
+        return fail(QS_ERR_OOM, "%s: host allocation failed", where);
     }
+}
+
+qs_status qs_adjoint_grad(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                          const double *theta_zz, const double *theta_x, void *lambda_buf, size_t lambda_bytes,
+                          double *exp_c, double *d_theta_zz, double *d_theta_x)
+{
+    return adjoint_entry(s, diag_dev, w_total_tenths, p, theta_zz, theta_x, nullptr, 0, false, lambda_buf,
+                         lambda_bytes, exp_c, d_theta_zz, d_theta_x, "qs_adjoint_grad");
+}
+
+qs_status qs_adjoint_ckpt_bytes(qs_state s, int p, size_t *bytes)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (p < 1) return fail(QS_ERR_ARG, "p must be >= 1 (got %d)", p);
+    if (p > (1 << 20)) return fail(QS_ERR_ARG, "p must be <= 2^20 (got %d)", p);
+    if (!bytes) return fail(QS_ERR_ARG, "null output");
+    try {
+        *bytes = (size_t)ckpt_states(s, p) * qs_state_bytes(s->n, s->prec);
+    } catch (...) {
+        return fail(QS_ERR_OOM, "qs_adjoint_ckpt_bytes: host allocation failed");
+    }
+    return QS_OK;
+}
+
+qs_status qs_adjoint_grad_store(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
+                                const double *theta_zz, const double *theta_x, void *ckpt_buf, size_t ckpt_bytes,
+                                void *lambda_buf, size_t lambda_bytes, double *exp_c, double *d_theta_zz,
+                                double *d_theta_x)
+{
+    return adjoint_entry(s, diag_dev, w_total_tenths, p, theta_zz, theta_x, ckpt_buf, ckpt_bytes, true,
+                         lambda_buf, lambda_bytes, exp_c, d_theta_zz, d_theta_x, "qs_adjoint_grad_store");
 }
 
 qs_status qs_profile(qs_state s, int enable)
@@ -1414,7 +1501,7 @@ int qs_batch_plan_check(int count, const qs_circuit *circuits, int prec, char *m
         lastk[s.circuit] = i;
         ++seen[s.circuit];
         const char *psi = (const char *)s.pp.psi, *dg = (const char *)s.pp.diag;
-        if (psi != lo + b.off_psi[s.circuit] || dg != lo + b.off_diag[s.circuit] ||
+        if (psi != lo + b.off_psi[s.circuit] || s.pp.psi_out != s.pp.psi || dg != lo + b.off_diag[s.circuit] ||
             (s.kind >= 1 && (const char *)s.pp.lam != lo + b.off_lam[s.circuit]) || psi < lo || psi >= hi)
             return bad("step %d: buffer pointers", i);
         if (s.pp.has_phase != (s.tab_off >= 0)) return bad("step %d: phase table", i);

@@ -47,6 +47,9 @@ struct RxStage {
 struct PassProg {
     void *psi;            // state (float2 / double2)
     void *lam;            // adjoint vector (reverse kernels only)
+    void *psi_out;        // where the pass stores psi: psi (in place), another
+                          // buffer (checkpointing forward), or null (reverse
+                          // pass reading a checkpoint: psi is not stored)
     const int32_t *diag;  // cost diagonal in tenths
     double *partials;     // kSlots doubles per workgroup
     int64_t ntiles;       // 2^(n - T); workgroups loop over tiles

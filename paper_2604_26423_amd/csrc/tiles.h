@@ -303,7 +303,8 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     const bool has_post = KS ? (SH & kShPost) != 0 : pp.has_post != 0;
     const bool init = KS ? (SH & kShInit) != 0 : pp.init != 0;
     const bool readout = KS ? (SH & kShReadout) != 0 : pp.readout != 0;
-    V *psi = reinterpret_cast<V *>(pp.psi);
+    const V *psi = reinterpret_cast<const V *>(pp.psi);
+    V *out = reinterpret_cast<V *>(pp.psi_out);
     const int32_t *diag = pp.diag;
     const bool need_diag = has_phase || readout;
     const int dwin = has_phase ? pp.phase_win : pp.final_win;
@@ -344,7 +345,7 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
             acc[1] += pr * (double)dg[r];
         }
     }
-    for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { psi[x] = v[r]; });
+    for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { out[x] = v[r]; });
 }
 
 // Turnaround on one tile: apply the last forward pass, read out the norm and
@@ -445,7 +446,8 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
 // gzz of the phase layer, acc[2] += gx of the pre layer.  The reverse of the
-// first forward pass (init) only accumulates and writes nothing.  LATE: dg is
+// first forward pass (init) only accumulates and writes nothing; with
+// pp.psi_out null only lambda is stored (checkpointed psi).  LATE: dg is
 // loaded here at the phase point rather than by the caller.
 template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true, bool LATE = false>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
@@ -461,7 +463,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     const bool has_phase = KS ? (SH & kShPhase) != 0 : pp.has_phase != 0;
     const bool has_post = KS ? (SH & kShPost) != 0 : pp.has_post != 0;
     const bool init = KS ? (SH & kShInit) != 0 : pp.init != 0;
-    V *psi = reinterpret_cast<V *>(pp.psi);
+    V *psi = reinterpret_cast<V *>(pp.psi_out);
     V *lam = reinterpret_cast<V *>(pp.lam);
     const R fpre = (R)pp.fpre, fpost = (R)pp.fpost;
     const Geom gg = geom_of(pp);
@@ -511,10 +513,15 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (!init) {
-        for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
-            psi[g] = p[r];
-            lam[g] = l[r];
-        });
+        if (psi) {
+            for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0), [&](int r, int64_t g) {
+                psi[g] = p[r];
+                lam[g] = l[r];
+            });
+        } else {  // psi of the next reverse pass comes from a checkpoint
+            for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
+                             [&](int r, int64_t g) { lam[g] = l[r]; });
+        }
     }
 }
 

@@ -174,11 +174,24 @@ class Simulator:
         cut = np.arange(len(mass), dtype=np.float64)
         return cut / self.cmax, mass / mass.sum()
 
-    def adjoint(self, theta_zz, theta_x):
+    def adjoint(self, theta_zz, theta_x, mode: str = "uncompute"):
+        """(E, dE/dtheta_zz, dE/dtheta_x).  mode "uncompute" undoes every pass on
+        psi (two state vectors at any depth); "store" keeps the state after every
+        tile pass in a checkpoint buffer (qs_adjoint_ckpt_bytes) and reads it back."""
         if self.lam is None:
             self.lam = self.torch.empty_like(self.psi)
-        return _qs.qs_adjoint_grad(self.handle, self.diag, self.w_total, theta_zz, theta_x, self.lam,
-                                   self.lam.numel() * self.lam.element_size())
+        lb = self.lam.numel() * self.lam.element_size()
+        if mode == "uncompute":
+            return _qs.qs_adjoint_grad(self.handle, self.diag, self.w_total, theta_zz, theta_x, self.lam, lb)
+        if mode != "store":
+            raise ValueError(f"mode must be 'uncompute' or 'store', not {mode!r}")
+        nb = _qs.qs_adjoint_ckpt_bytes(self.handle, len(np.atleast_1d(theta_zz)))
+        ck = self.torch.empty(max(nb, 1), dtype=self.torch.uint8, device=self.device) if nb else None
+        try:
+            return _qs.qs_adjoint_grad_store(self.handle, self.diag, self.w_total, theta_zz, theta_x, ck, nb,
+                                             self.lam, lb)
+        finally:
+            del ck
 
     def release_adjoint(self):
         self.lam = None

@@ -38,7 +38,8 @@ KIND_KERNEL = {"pass": "pass_kernel", "pass_phase": "pass_kernel", "adjoint": "a
 EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free", "qs_state_ptr",
            "qs_set_stream", "qs_init_plus", "qs_cost_diagonal", "qs_cost_diagonal_sym", "qs_apply_cost_layer", "qs_apply_mixer",
            "qs_forward", "qs_expect", "qs_sample", "qs_cost_histogram", "qs_layout_index", "qs_get_amplitudes",
-           "qs_set_amplitudes", "qs_adjoint_grad", "qs_profile", "qs_profile_read",
+           "qs_set_amplitudes", "qs_adjoint_grad", "qs_adjoint_grad_store", "qs_adjoint_ckpt_bytes",
+           "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
            "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free"]
 QS_BATCH_MAX_QUBITS = 30
@@ -94,6 +95,8 @@ def lib() -> ctypes.CDLL:
         "qs_get_amplitudes": ([vp, i64, i64, vp, i32], i32),
         "qs_set_amplitudes": ([vp, i64, i64, vp, i32], i32),
         "qs_adjoint_grad": ([vp, vp, i64, i32, vp, vp, vp, sz, _c_dbl_p, vp, vp], i32),
+        "qs_adjoint_grad_store": ([vp, vp, i64, i32, vp, vp, vp, sz, vp, sz, _c_dbl_p, vp, vp], i32),
+        "qs_adjoint_ckpt_bytes": ([vp, i32, ctypes.POINTER(sz)], i32),
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
         "qs_plan_check": ([i32, i32, i32, ctypes.c_char_p, sz], i32),
@@ -293,6 +296,29 @@ def qs_adjoint_grad(s, diag_dev, w_total_tenths: int, theta_zz, theta_x, lambda_
                                  _ptr(lambda_buf), int(lambda_bytes), ctypes.byref(e),
                                  gzz.ctypes.data if p else None, gx.ctypes.data if p else None))
     return e.value, gzz, gx
+
+
+def qs_adjoint_grad_store(s, diag_dev, w_total_tenths: int, theta_zz, theta_x, ckpt_buf=None,
+                          ckpt_bytes: int = 0, lambda_buf=None, lambda_bytes: int = 0) -> tuple:
+    """Store mode of the adjoint (checkpointed psi).  Returns (E, dE/dtheta_zz[p], dE/dtheta_x[p])."""
+    tzz, tx = _f64(theta_zz), _f64(theta_x)
+    if tzz.shape != tx.shape:
+        raise ValueError("theta_zz and theta_x must have the same length")
+    p = len(tzz)
+    gzz, gx, e = np.empty(p), np.empty(p), ctypes.c_double()
+    _check(lib().qs_adjoint_grad_store(s, _ptr(diag_dev), int(w_total_tenths), p,
+                                       tzz.ctypes.data if p else None, tx.ctypes.data if p else None,
+                                       _ptr(ckpt_buf), int(ckpt_bytes), _ptr(lambda_buf), int(lambda_bytes),
+                                       ctypes.byref(e), gzz.ctypes.data if p else None,
+                                       gx.ctypes.data if p else None))
+    return e.value, gzz, gx
+
+
+def qs_adjoint_ckpt_bytes(s, p: int) -> int:
+    """Checkpoint bytes qs_adjoint_grad_store needs for p layers."""
+    b = ctypes.c_size_t()
+    _check(lib().qs_adjoint_ckpt_bytes(s, int(p), ctypes.byref(b)))
+    return int(b.value)
 
 
 def qs_profile(s, enable: bool) -> None:

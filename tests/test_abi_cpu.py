@@ -90,6 +90,32 @@ def test_entry_point_validation(fake_state):
     assert "null state" in expect_status(qs.QS_ERR_ARG, qs.qs_init_plus, None)
 
 
+def test_store_mode_checkpoint_size_and_validation(fake_state):
+    s = fake_state   # n = 16: two tile passes per layer (13 + 3 qubits), P = p + 1 passes
+    sb = qs.qs_state_bytes(16, qs.QS_C64)
+    assert qs.qs_adjoint_ckpt_bytes(s, 1) == 0
+    assert qs.qs_adjoint_ckpt_bytes(s, 3) == 2 * sb       # outputs of passes 0 .. P-3
+    expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_ckpt_bytes, s, 0)
+    diag, lam, ck = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
+    a = (s, diag, 100, [0.1, 0.2, 0.3], [0.3, 0.2, 0.1])
+    assert "null checkpoint" in expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad_store, *a, None, 0, lam, sb)
+    assert "too small" in expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad_store, *a, ck, 2 * sb - 1, lam, sb)
+    expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad_store, *a, ck + 8, 4 * sb, lam, sb)       # misaligned
+    assert "overlaps" in expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad_store, *a, FAKE - sb, 2 * sb, lam, sb)
+    assert "overlaps" in expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad_store, *a, lam + sb // 2, 2 * sb, lam, sb)
+    small = qs.qs_alloc(10, qs.QS_C64, FAKE, 8 << 10, 0)   # one workgroup holds the state
+    try:
+        assert qs.qs_adjoint_ckpt_bytes(small, 5) == 0
+    finally:
+        qs.lib().qs_free(small)
+    big = qs.qs_alloc(32, qs.QS_C64, FAKE, 8 << 32, 0)     # 13 + 10 + 9 qubits: P = 2p + 1
+    try:
+        assert qs.qs_adjoint_ckpt_bytes(big, 3) == 5 * (8 << 32)
+        assert qs.qs_adjoint_ckpt_bytes(big, 10) == 19 * (8 << 32)
+    finally:
+        qs.lib().qs_free(big)
+
+
 def test_cost_diagonal_validation():
     w = np.ones(45, dtype=np.int32)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 0, w, FAKE, 0)

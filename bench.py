@@ -11,14 +11,15 @@ measured inside every timed step with HIP events on the library's stream.
 Also reported: the same forward in complex128, the forward+adjoint / forward
 time ratio, HBM bandwidth of the dominant kernel against the 8 TB/s peak,
 and the CPU oracle timed on the host (a bounded sample, see cpu_baseline).
-Side runs in the same line (not part of the headline value): the exact
+Side runs in the same line (not part of the headline value): the store mode
+of the adjoint (per-pass checkpoints, 160 GiB at n = 32), the exact
 cut-value histogram of the final state, the complement-symmetric half-state
 layout, the 512-circuit batched forward+adjoint, the depolarizing-noise
 trajectories (K_12, p = 10, and the overlap study of Sec. II-C), and the
 30-qubit depth sweep (K_30, seed 5, p = 3, 6, 10, 50, 100).
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-c128] [--no-sym]
-                       [--no-batch] [--no-noise] [--no-sweep30] [--noise-only]
+                       [--no-store] [--no-batch] [--no-noise] [--no-sweep30] [--noise-only]
 """
 import argparse
 import json
@@ -290,6 +291,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=27, help="qubits of the CPU oracle sample")
     ap.add_argument("--no-sweep30", action="store_true", help="skip the 30-qubit depth sweep")
     ap.add_argument("--no-sym", action="store_true", help="skip the complement-symmetric layout run")
+    ap.add_argument("--no-store", action="store_true", help="skip the store-mode (checkpointed) adjoint run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched forward+adjoint")
     ap.add_argument("--no-noise", action="store_true", help="skip the noisy-trajectory runs")
     ap.add_argument("--noise-only", action="store_true",
@@ -419,6 +421,37 @@ def main():
                     "grad_theta_zz": res["grad_zz"], "grad_theta_x": res["grad_x"]},
         "wall_s_timed": round(wall, 3),
     }
+
+    if not args.no_store:
+        # the store mode of the adjoint: per-pass checkpoints instead of
+        # undoing the passes on psi (5 states of 32 GiB at n=32, p=3)
+        need = Q.qs_adjoint_ckpt_bytes(sim.handle, p)
+        torch.cuda.empty_cache()
+        free = torch.cuda.mem_get_info()[0]
+        if free < need + (4 << 30):
+            out["store_mode"] = {"skipped": f"needs {need / 2 ** 30:.0f} GiB of checkpoints, "
+                                            f"{free / 2 ** 30:.0f} GiB free"}
+        else:
+            ck = torch.empty(need, dtype=torch.uint8, device="cuda")
+            ts = []
+            for i in range(3):
+                a = ev()
+                es, szz, sx = Q.qs_adjoint_grad_store(sim.handle, sim.diag, sim.w_total, tzz, tx, ck, need,
+                                                      sim.lam, lam_bytes)
+                bb = ev()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(bb))
+                log(f"store-mode forward+adjoint {i}: {ts[-1]:.1f} ms")
+            del ck
+            torch.cuda.empty_cache()
+            t_st = float(np.median(ts[1:]))
+            uzz, ux = np.array(res["grad_zz"]), np.array(res["grad_x"])
+            scale = max(np.abs(uzz).max(), np.abs(ux).max())
+            out["store_mode"] = {"forward_plus_adjoint_ms": round(t_st, 3), "over_fwd": round(t_st / float(t_fwd), 3),
+                                 "checkpoint_gib": need / 2 ** 30,
+                                 "grad_rel_diff_vs_uncompute": max(np.abs(szz - uzz).max(),
+                                                                   np.abs(sx - ux).max()) / scale,
+                                 "exp_c_rel_diff": abs(es - res["exp_c"]) / res["exp_c"]}
 
     if not args.no_c128:
         # the same forward in complex128 (64 GiB state), sharing the diagonal

@@ -227,7 +227,8 @@ qs_status qs_cost_histogram(qs_state s, const int32_t *diag_dev, int32_t nbins, 
  *   d_theta_zz[k] = dE/dtheta_zz[k],  d_theta_x[k] = dE/dtheta_x[k]
  * (host arrays of length p >= 1; exp_c receives E).  The reverse sweep
  * undoes every layer on the state and on the adjoint vector (no stored
- * checkpoints), so it needs exactly two state vectors for any p.
+ * checkpoints; qs_adjoint_grad_store below keeps them instead), so it needs
+ * exactly two state vectors for any p.
  * lambda_buf: caller-owned device buffer of lambda_bytes >= qs_state_bytes
  * for the adjoint vector, or NULL to let the library allocate it for the call.
  * On return the state buffer holds an intermediate of the reverse sweep (its

@@ -245,7 +245,9 @@ def test_adjoint_c128_vs_oracle(n, p):
     sim.close()
 
 
-@pytest.mark.parametrize("n,p", [(9, 3), (14, 3), (18, 5)])
+# n = 14, 18: junctions whose stages end in one-bit windows; n = 19: a
+# junction of two-bit last windows; n = 20: three-bit (the generic kernel)
+@pytest.mark.parametrize("n,p", [(9, 3), (14, 3), (18, 5), (19, 3), (20, 2)])
 def test_adjoint_c64_vs_oracle(n, p):
     w = workloads.complete_graph_tenths(n, 60 + n)
     tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(p, 0.6, 0.6))

@@ -159,7 +159,11 @@ __device__ __forceinline__ void noise_layer(const NoiseProg &np, int k, V (&v)[N
         const uint8_t *cl = codes + (k % kNoiseChunk) * G;
         uint32_t carry = 0, ez = 0;
         int nf = 0, wf = 0, ph = 0, cnt = 0;
-        for (int base = 0; base < G; base += WL) {
+        // most layers draw no error: then every sum below stays zero
+        bool any = false;
+        for (int base = 0; base < G; base += WL) any |= base + lane < G && cl[base + lane] != 0;
+        const int first = __ballot(any) != 0 ? 0 : G;
+        for (int base = first; base < G; base += WL) {
             const int e = base + lane;
             const bool valid = e < G;
             const int code = valid ? cl[e] : 0;

@@ -262,6 +262,27 @@ def test_adjoint_c64_vs_oracle(n, p):
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("mode", ["uncompute", "store"])
+def test_adjoint_large_angles_general_stage_code(precision, mode):
+    """Mixer angles with |cos(theta_x / 2)| < 1/2 in some layers: those passes
+    take the general (non-tangent) stage code in both directions."""
+    n, p = 16, 4
+    w = workloads.complete_graph_tenths(n, 33)
+    tzz = np.array([0.3, -0.7, 0.5, 0.2])
+    tx = np.array([2.6, -0.4, -2.9, 1.1])          # |tx / 2| > pi / 3 in layers 0 and 2
+    assert (np.abs(np.cos(tx / 2)) < 0.5).sum() == 2
+    sim = sim_for(w, precision)
+    e, gzz, gx = sim.adjoint(tzz, tx, mode=mode)
+    e_ref, rzz, rx = oracle.adjoint(n, w, tzz, tx)
+    scale = max(np.abs(rzz).max(), np.abs(rx).max())
+    err = max(np.abs(gzz - rzz).max(), np.abs(gx - rx).max()) / scale
+    say(f"  {precision} {mode}: <C> rel {abs(e - e_ref) / e_ref:.2e}, gradient rel {err:.2e}")
+    tol, etol = (1e-4, 1e-6) if precision == "c64" else (1e-10, 1e-12)
+    assert abs(e - e_ref) <= etol * e_ref and err <= tol
+    sim.close()
+
+
 def test_adjoint_vs_finite_differences_then_forward_again():
     n, p = 15, 3
     w = workloads.complete_graph_tenths(n, 77)

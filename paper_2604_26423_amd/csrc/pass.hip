@@ -3,9 +3,10 @@
 // tiles.h; these kernels build the workgroup's phase table, walk tiles and
 // reduce the workgroup's partial sums.
 //
-// Forward passes launch one workgroup per tile.  The turnaround and the
-// reverse passes run one persistent workgroup per CU that loads the next
-// tile's vectors into registers while it works on the current tile.
+// Forward passes launch one workgroup per tile.  The complex64 adjoint
+// kernels in tangent form do the same, two workgroups per CU; the others run
+// one persistent workgroup per CU that loads the next tile's vectors into
+// registers while it works on the current tile (see adjoint_variant).
 #include <stdlib.h>
 
 #include "tiles.h"
@@ -133,7 +134,8 @@ int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
     // Forward passes: one tile per workgroup -- the hardware dispatcher's
     // dynamic assignment of workgroups to CUs overlaps loads, butterflies and
     // stores across workgroups better than a persistent loop (measured on
-    // MI355X).  Adjoint kernels: one persistent workgroup per CU.
+    // MI355X).  Persistent adjoint kernels: one workgroup per CU (the
+    // one-tile adjoint variants launch one workgroup per tile, tile_grid).
     (void)prec;
     if (adjoint == 1 || adjoint == 2) {
         int dev = 0, cus = 256;

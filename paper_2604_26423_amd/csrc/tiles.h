@@ -90,11 +90,11 @@ __device__ __forceinline__ void phase_factors(const V *tab, int levels, const in
     }
 }
 
-// v[r] *= conj(phase factor of C[r]) for two vectors, half of the registers at
-// a time: the runtime loop over levels carries only the half's factors, not
-// the two vectors.
+// v[r] *= conj(phase factor of C[r]) for two vectors, a quarter of the
+// registers at a time: the runtime loop over levels carries only that
+// quarter's factors, not the two vectors.
 template <typename V, int NR>
-__device__ __forceinline__ void unphase_halves(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
+__device__ __forceinline__ void unphase_quarters(const V *tab, int levels, const int32_t (&C)[NR], V (&a)[NR],
                                                V (&b)[NR])
 {
     constexpr int H = NR >= 4 ? NR / 4 : 1;
@@ -498,7 +498,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         // vectors' values at the phase point live through that stage
         asm volatile("" : "+v"(gz));
         acc[1] += -0.2 * (double)gz * (fold && has_post ? pp.fpost * pp.fpost : 1.0);
-        if (!init) unphase_halves(tab, pp.phase_levels, dg, p, l);
+        if (!init) unphase_quarters(tab, pp.phase_levels, dg, p, l);
     }
     if (has_pre) {
         double gpre = 0.0;

@@ -269,16 +269,17 @@ def _autograd():
     class ExpectC(torch.autograd.Function):
         """<C>(gammas, betas) with the adjoint gradient of libqs.
 
-        forward(gammas, betas, sim, convention) runs the circuit and the
-        reverse sweep once; backward scales the stored gradient.
+        forward(gammas, betas, sim, convention, mode) runs the circuit and the
+        reverse sweep once (mode "uncompute" or "store", see
+        Simulator.adjoint); backward scales the stored gradient.
         """
 
         @staticmethod
-        def forward(ctx, gammas, betas, sim, convention="paper"):
+        def forward(ctx, gammas, betas, sim, convention="paper", mode="uncompute"):
             g = gammas.detach().cpu().double().numpy()
             b = betas.detach().cpu().double().numpy()
             tzz, tx = to_gate_angles(g, b, convention)
-            e, gzz, gx = sim.adjoint(tzz, tx)
+            e, gzz, gx = sim.adjoint(tzz, tx, mode=mode)
             dg, db = gate_grad_to_schedule(gzz, gx, convention)
             ctx.save_for_backward(torch.as_tensor(dg, dtype=gammas.dtype),
                                   torch.as_tensor(db, dtype=betas.dtype))
@@ -287,7 +288,7 @@ def _autograd():
         @staticmethod
         def backward(ctx, grad_out):
             dg, db = ctx.saved_tensors
-            return grad_out.to(dg.dtype) * dg, grad_out.to(db.dtype) * db, None, None
+            return grad_out.to(dg.dtype) * dg, grad_out.to(db.dtype) * db, None, None, None
 
     return ExpectC
 
@@ -295,12 +296,13 @@ def _autograd():
 _ExpectC = None
 
 
-def expect_c(gammas, betas, sim: Simulator, convention: str = "paper"):
-    """Differentiable <C> as a function of per-layer (gamma_k, beta_k) CPU tensors."""
+def expect_c(gammas, betas, sim: Simulator, convention: str = "paper", mode: str = "uncompute"):
+    """Differentiable <C> as a function of per-layer (gamma_k, beta_k) CPU tensors;
+    mode selects the adjoint's reverse sweep ("uncompute" or "store")."""
     global _ExpectC
     if _ExpectC is None:
         _ExpectC = _autograd()
-    return _ExpectC.apply(gammas, betas, sim, convention)
+    return _ExpectC.apply(gammas, betas, sim, convention, mode)
 
 
 class Batch:

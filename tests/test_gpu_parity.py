@@ -299,14 +299,15 @@ def test_adjoint_vs_finite_differences_then_forward_again():
     sim.close()
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("n,mode", [(10, "uncompute"), (15, "store")])
+def test_autograd_function(n, mode):
     from paper_2604_26423_amd import expect_c
-    n, p = 10, 3
+    p = 3
     w = workloads.complete_graph_tenths(n, 3)
     sim = sim_for(w, "c128")
     gam = torch.tensor([0.1, 0.3, 0.5], dtype=torch.float64, requires_grad=True)
     bet = torch.tensor([0.5, 0.3, 0.1], dtype=torch.float64, requires_grad=True)
-    e = expect_c(gam, bet, sim, "paper")
+    e = expect_c(gam, bet, sim, "paper", mode)
     e.backward()
     tzz, tx = oracle.gate_angles(gam.detach().numpy(), bet.detach().numpy(), "paper")
     e_ref, rzz, rx = oracle.adjoint(n, w, tzz, tx)

@@ -237,6 +237,45 @@ def test_n33_adjoint():
     s.close()
 
 
+@pytest.mark.parametrize("p,delta", [(10, 0.3), (3, 0.9)])
+def test_n32_adjoint_vs_finite_differences(p, delta):
+    """The complex64 adjoint gradient at n = 32 against central differences
+    (h = 1e-4) of the complex128 forward, for the first and last layer's two
+    angles: a property of the gradient at any size.  At p = 3 the store mode
+    (160 GiB of checkpoints) is checked too; at p = 10 its 19 checkpoints
+    would not fit."""
+    n, h = 32, 1e-4
+    run = workloads.LARGE
+    w = run.weights()
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(p, delta, delta))
+    say(f"n=32 p={p} delta={delta}: complex64 adjoint")
+    s64 = sim(w, "c64")
+    e64, gzz, gx = s64.adjoint(tzz, tx)
+    grads = [("uncompute", gzz, gx)]
+    if p == 3:
+        _, szz, sx = s64.adjoint(tzz, tx, mode="store")
+        grads.append(("store", szz, sx))
+    release(s64)
+    s128 = sim(w, "c128")
+    fd = {}
+    for name, ang in (("zz", tzz), ("x", tx)):
+        for k in (0, p - 1):
+            a, b = ang.copy(), ang.copy()
+            a[k] += h
+            b[k] -= h
+            ep, _ = s128.forward(*((a, tx) if name == "zz" else (tzz, a)))
+            em, _ = s128.forward(*((b, tx) if name == "zz" else (tzz, b)))
+            fd[name, k] = (ep - em) / (2 * h)
+    e128, _ = s128.forward(tzz, tx)
+    scale = max(np.abs(gzz).max(), np.abs(gx).max())
+    for mode, a_zz, a_x in grads:
+        for (name, k), ref in fd.items():
+            got = a_zz[k] if name == "zz" else a_x[k]
+            say(f"  {mode} d/dtheta_{name}[{k}]: adjoint {got:.9f}, central difference {ref:.9f}")
+            assert abs(got - ref) <= 1e-4 * scale
+    assert abs(e64 - e128) <= 1e-6 * e128
+
+
 def test_n32_symmetric_layout_matches_full_layout():
     """The complement-symmetric half state against the full layout on the
     benchmark circuit: <C>, norm and the adjoint gradient."""

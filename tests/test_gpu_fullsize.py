@@ -237,18 +237,17 @@ def test_n33_adjoint():
     s.close()
 
 
-@pytest.mark.parametrize("p,delta", [(10, 0.3), (3, 0.9)])
-def test_n32_adjoint_vs_finite_differences(p, delta):
+@pytest.mark.parametrize("run", workloads.LARGE_SWEEP, ids=lambda r: r.name)
+def test_n32_adjoint_vs_finite_differences(run):
     """The complex64 adjoint gradient at n = 32 against central differences
     (h = 1e-4) of the complex128 forward, for the first and last layer's two
     angles: a property of the gradient at any size.  At p = 3 the store mode
     (160 GiB of checkpoints) is checked too; at p = 10 its 19 checkpoints
     would not fit."""
-    n, h = 32, 1e-4
-    run = workloads.LARGE
+    n, h, p = run.n, 1e-4, run.p
     w = run.weights()
-    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(p, delta, delta))
-    say(f"n=32 p={p} delta={delta}: complex64 adjoint")
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(p, run.delta_gamma, run.delta_beta))
+    say(f"{run.name}: complex64 adjoint")
     s64 = sim(w, "c64")
     e64, gzz, gx = s64.adjoint(tzz, tx)
     grads = [("uncompute", gzz, gx)]

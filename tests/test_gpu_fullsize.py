@@ -71,6 +71,34 @@ def sampled_indices(n, count, seed):
     return np.unique(np.concatenate([xs, np.asarray(fixed, dtype=np.uint64)]))
 
 
+def test_k26_config_c64_c128_and_oracle():
+    """The 26-qubit configuration (K26, seed 1, p = 3, D = 0.6): both GPU
+    precisions against the oracle's state, <C> and r with the exhaustive
+    C(x*), and 10,000 shots bit-exact with the oracle's sampler on the GPU
+    state."""
+    run = workloads.MEDIUM
+    n, w = run.n, run.weights()
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(run.p, run.delta_gamma, run.delta_beta))
+    say("K26 oracle state")
+    ref = oracle.simulate(n, w, tzz, tx, mode=1)
+    e_ref, _ = oracle.expect(ref, oracle.cost_diagonal(n, w))
+    cmax = GOLDEN[(n, run.seed)]["cmax_tenths"]
+    for prec, tol, etol in (("c64", 1e-5, 1e-6), ("c128", 1e-12, 1e-12)):
+        s = sim(w, prec)
+        assert s.cmax == cmax
+        e, _ = s.forward(tzz, tx)
+        torch.cuda.synchronize()
+        psi = s.amplitudes().cpu().numpy()
+        err = np.abs(psi - ref).max()
+        say(f"  {prec}: max-abs {err:.3e}, <C> rel {abs(e - e_ref) / e_ref:.3e}, r {s.ratio(e):.9f}")
+        assert err <= tol and abs(e - e_ref) <= etol * e_ref
+        assert abs(s.ratio(e) - e_ref / (cmax / 10)) <= etol * e_ref / (cmax / 10)
+        shots = s.sample(run.shots, seed=run.seed)
+        assert np.array_equal(shots, oracle.sample(psi, run.seed, run.shots))
+        release(s)
+        del psi
+
+
 @pytest.mark.parametrize("n,seed", [(32, 2), (33, 3), (34, 3)])
 def test_cost_diagonal_full_size(n, seed):
     from paper_2604_26423_amd import qs

@@ -62,6 +62,27 @@ def test_cost_diagonal_large_weights():
     sim.close()
 
 
+def test_k12_config_vs_oracle():
+    """The 12-qubit configuration (K12, seed 0, p = 3, D = 0.6, complex128):
+    amplitudes, <C>, brute-force C(x*), r and 1,000 shots against the oracle."""
+    run = workloads.SMALL
+    n, w = run.n, run.weights()
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(run.p, run.delta_gamma, run.delta_beta))
+    sim = sim_for(w, "c128")
+    e, nrm = sim.forward(tzz, tx)
+    psi = host_state(sim)
+    ref = oracle.simulate(n, w, tzz, tx, mode=0)
+    e_ref, n_ref = oracle.expect(ref, oracle.cost_diagonal(n, w))
+    cmax = oracle.cmax_direct(n, w)
+    assert np.abs(psi - ref).max() <= 1e-12
+    assert abs(e - e_ref) <= 1e-12 * e_ref and abs(nrm - 1) <= 1e-12
+    assert sim.cmax == cmax and abs(sim.ratio(e) - e_ref / (cmax / 10)) <= 1e-12
+    shots = sim.sample(run.shots, run.seed)
+    assert np.array_equal(shots, oracle.sample(psi, run.seed, run.shots))
+    say(f"K12: <C> {e:.12f}, r {sim.ratio(e):.9f}, r_shots {sim.shots_ratio(shots):.4f}")
+    sim.close()
+
+
 # ---------------------------------------------------------------- forward
 CASES = [(2, 1), (5, 3), (12, 3), (13, 2), (14, 3), (15, 4), (17, 1), (18, 3), (20, 4), (22, 2), (24, 3)]
 

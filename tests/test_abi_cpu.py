@@ -116,6 +116,15 @@ def test_store_mode_checkpoint_size_and_validation(fake_state):
         qs.lib().qs_free(big)
 
 
+def test_no_device_is_a_hip_error_not_a_crash():
+    """Library-allocated memory without a GPU: QS_ERR_HIP with HIP's message."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    msg = expect_status(qs.QS_ERR_HIP, qs.qs_alloc, 10, qs.QS_C64, None, 0, 0)
+    assert "qs_alloc" in msg
+
+
 def test_cost_diagonal_validation():
     w = np.ones(45, dtype=np.int32)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 0, w, FAKE, 0)

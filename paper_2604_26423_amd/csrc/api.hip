@@ -192,6 +192,14 @@ RxStage rx_stage(double theta, int m, double *factor)
     return st;
 }
 
+// Last window of a sequence.  A sequence longer than kMaxWindows (flagged by
+// plan_windows) never occurs for a supported n -- qs_plan_check verifies every
+// plan -- and the clamp keeps the read inside the array regardless.
+static int last_window(const WinSeq &w)
+{
+    return w.s[std::min(std::max(w.cnt, 1), kMaxWindows) - 1];
+}
+
 PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassGeom &g, const KSpec &k,
                        const Circuit &cc, int tb, int sym = 0)
 {
@@ -219,15 +227,15 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     pp.fpre = pp.fpost = 1.0;
     if (pp.has_pre) {
         pp.A = plan_windows(tb, g.targets, g.pairs, T, tb);
-        pp.B = plan_windows(pp.A.s[pp.A.cnt - 1], g.targets, g.pairs, T, tb);
+        pp.B = plan_windows(last_window(pp.A), g.targets, g.pairs, T, tb);
         pp.pre = rx_stage(cc.tx[k.pre], pp.ntargets, &pp.fpre);
     } else {
         pp.B = plan_windows(tb, g.targets, g.pairs, T, tb);
     }
     if (pp.has_post) pp.post = rx_stage(cc.tx[k.post], pp.ntargets, &pp.fpost);
     pp.factor = pp.fpre * pp.fpost;
-    pp.phase_win = pp.has_pre ? pp.A.s[pp.A.cnt - 1] : pp.load_win;
-    pp.final_win = pp.B.s[pp.B.cnt - 1];
+    pp.phase_win = pp.has_pre ? last_window(pp.A) : pp.load_win;
+    pp.final_win = last_window(pp.B);
     if (pp.has_phase) pp.theta_zz = cc.tzz[k.phase];
     pp.W = cc.W;
     pp.phase_levels = phase_table_levels(cc.W);

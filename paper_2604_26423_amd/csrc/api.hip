@@ -9,7 +9,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +99,19 @@ struct DevBuf {
 };
 
 }  // namespace
+
+namespace qs {
+qs_status set_error(qs_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+}  // namespace qs
 
 struct qs_state_s {
     int n = 0, prec = 0;  // n: stored index bits (qubits, or qubits - 1 when sym)
@@ -679,11 +694,11 @@ struct DiagScratch {
     size_t off_low, off_wg, off_tmp, off_res, total;
 };
 
-DiagScratch diag_scratch_layout(int nmax, int nres)
+DiagScratch diag_scratch_layout(int nmax, int nres, int sym = 0)
 {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     DiagScratch L;
-    const int64_t nwg = diag_wg_count(nmax);
+    const int64_t nwg = diag_wg_count(nmax, sym);
     L.off_low = up((size_t)nmax * nmax * 4);
     L.off_wg = L.off_low + 8192 * 4;
     L.off_tmp = L.off_wg + up((size_t)nwg * 4);
@@ -802,6 +817,25 @@ qs_status qs_init_plus(qs_state s)
 }
 
 namespace {
+// Scratch of qs_cost_diagonal: one grow-only buffer per device, held by a call
+// from its first copy until its stream has finished (every call synchronises),
+// so calls from several threads take turns instead of allocating.  The buffers
+// live until the process ends.
+struct DiagCache {
+    std::mutex mu;
+    DevBuf buf;
+};
+
+DiagCache *diag_cache(int dev)
+{
+    static std::mutex map_mu;
+    static std::map<int, DiagCache *> caches;
+    std::lock_guard<std::mutex> g(map_mu);
+    DiagCache *&c = caches[dev];
+    if (!c) c = new DiagCache();  // never freed: device memory outlives static destructors
+    return c;
+}
+
 qs_status cost_diagonal_impl(int n, int sym, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
                              int32_t *cmax_tenths, void *hip_stream)
 {
@@ -812,14 +846,17 @@ qs_status cost_diagonal_impl(int n, int sym, const int32_t *w_tenths, int32_t *d
         int64_t W = 0;
         if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
         hipStream_t st = (hipStream_t)hip_stream;
-        const DiagScratch L = diag_scratch_layout(n, 1);
-        char *scratch = nullptr;
-        HIPCHK(hipMalloc(&scratch, L.total), "qs_cost_diagonal");
+        const DiagScratch L = diag_scratch_layout(n, 1, sym);
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev), "qs_cost_diagonal");
+        DiagCache *cache = diag_cache(dev);
+        std::lock_guard<std::mutex> lock(cache->mu);
+        HIPCHK(cache->buf.ensure(L.total), "qs_cost_diagonal");
+        char *scratch = (char *)cache->buf.p;
         hipError_t he = build_diagonal(n, wm, diag_dev, scratch, L, 0, st, sym);
         int32_t cmax = 0;
         if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch + L.off_res, 4, hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
-        (void)hipFree(scratch);
         if (he != hipSuccess) return hip_fail(he, "qs_cost_diagonal");
         if (w_total_tenths) *w_total_tenths = W;
         if (cmax_tenths) *cmax_tenths = cmax;

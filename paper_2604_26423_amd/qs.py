@@ -41,7 +41,8 @@ EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free
            "qs_set_amplitudes", "qs_adjoint_grad", "qs_adjoint_grad_store", "qs_adjoint_ckpt_bytes",
            "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
-           "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free"]
+           "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free",
+           "qs_bandwidth_probe"]
 QS_BATCH_MAX_QUBITS = 30
 QS_NOISE_MAX_QUBITS = 12
 QS_NOISE_MAX_LAYERS = 4096
@@ -49,6 +50,18 @@ QS_NOISE_MAX_LAYERS = 4096
 
 class QSCircuit(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("w_tenths", ctypes.c_void_p)]
+
+
+(QS_PROBE_READ, QS_PROBE_WRITE, QS_PROBE_COPY, QS_PROBE_UPDATE, QS_PROBE_PHASE, QS_PROBE_TILE) = range(6)
+PROBE_KINDS = {"read": QS_PROBE_READ, "write": QS_PROBE_WRITE, "copy": QS_PROBE_COPY, "update": QS_PROBE_UPDATE,
+               "phase": QS_PROBE_PHASE, "tile": QS_PROBE_TILE}
+QS_PROBE_NT_LOAD, QS_PROBE_NT_STORE = 1, 2
+
+
+class QSProbe(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("flags", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
+                ("unroll", ctypes.c_int), ("n", ctypes.c_int), ("c", ctypes.c_int), ("q0", ctypes.c_int),
+                ("swizzle", ctypes.c_int)]
 
 
 class QSError(RuntimeError):
@@ -109,6 +122,7 @@ def lib() -> ctypes.CDLL:
         "qs_noise_info": ([vp, _c_i64_p, _c_i32_p], i32),
         "qs_noise_run": ([vp, i32, vp, vp, dbl, u64, i64, i64, vp, vp, vp, vp], i32),
         "qs_noise_free": ([vp], i32),
+        "qs_bandwidth_probe": ([vp, vp, vp, sz, i32, vp, _c_dbl_p, _c_dbl_p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -420,3 +434,14 @@ def qs_noise_run(h, theta_zz, theta_x, eps: float, seed: int, traj0: int, ntraj:
 
 def qs_noise_free(h) -> None:
     _check(lib().qs_noise_free(h))
+
+
+def qs_bandwidth_probe(kind: int, a, b=None, nbytes: int = 0, reps: int = 5, flags: int = 0, wg_per_cu: int = 0,
+                       unroll: int = 0, n: int = 0, c: int = 0, q0: int = 0, swizzle: int = 1,
+                       stream=None) -> tuple:
+    """(ms per launch, bytes read + written per launch) of a data-movement probe (include/qs_probe.h)."""
+    pr = QSProbe(int(kind), int(flags), int(wg_per_cu), int(unroll), int(n), int(c), int(q0), int(swizzle))
+    ms, by = ctypes.c_double(), ctypes.c_double()
+    _check(lib().qs_bandwidth_probe(ctypes.byref(pr), _ptr(a), _ptr(b), int(nbytes), int(reps), _stream(stream),
+                                    ctypes.byref(ms), ctypes.byref(by)))
+    return ms.value, by.value

@@ -248,3 +248,23 @@ def test_noise_validation():
     assert qs.lib().qs_noise_create(12, 0, w.ctypes.data, 0, None) == qs.QS_ERR_ARG
     assert qs.lib().qs_noise_run(None, 1, None, None, 0.1, 1, 0, 1, FAKE, None, None, None) == qs.QS_ERR_ARG
     assert qs.lib().qs_noise_free(None) == qs.QS_OK
+
+
+def test_bandwidth_probe_validation():
+    """Probe arguments are checked before any GPU work; without a device a
+    valid call reports QS_ERR_HIP."""
+    def P(*a, **kw):
+        return qs.qs_bandwidth_probe(*a, stream=0, **kw)
+    MiB = 1 << 20
+    expect_status(qs.QS_ERR_ARG, P, 9, FAKE, FAKE, MiB)                           # kind
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB, flags=4)   # flags
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB, reps=0)
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE + 16, FAKE, MiB)       # alignment of a
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, None, MiB)            # copy needs b
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB + 16)       # size
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB, unroll=3)
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 20, n=20, c=3, q0=13)  # bytes != 2^n * 8
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 20, n=20, c=3, q0=11)  # tile beyond n
+    expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 13, n=13, c=0, q0=0)   # n too small
+    expect_status(qs.QS_ERR_HIP, P, qs.QS_PROBE_WRITE, FAKE, None, MiB)
+    expect_status(qs.QS_ERR_HIP, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 20, n=20, c=3, q0=10)

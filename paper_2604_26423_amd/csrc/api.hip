@@ -688,23 +688,9 @@ qs_status weight_matrix(int n, const int32_t *w, std::vector<int32_t> &wm, int64
     return QS_OK;
 }
 
-// Scratch for building diagonals of up to nmax qubits: weight matrix, low-bit
-// table, per-workgroup maxima (two levels) and `nres` int32 results.
-struct DiagScratch {
-    size_t off_low, off_wg, off_tmp, off_res, total;
-};
-
 DiagScratch diag_scratch_layout(int nmax, int nres, int sym = 0)
 {
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    DiagScratch L;
-    const int64_t nwg = diag_wg_count(nmax, sym);
-    L.off_low = up((size_t)nmax * nmax * 4);
-    L.off_wg = L.off_low + 8192 * 4;
-    L.off_tmp = L.off_wg + up((size_t)nwg * 4);
-    L.off_res = L.off_tmp + up((size_t)(nwg / 4096 + 2) * 4);
-    L.total = L.off_res + up((size_t)nres * 4);
-    return L;
+    return diag_scratch_plan(nmax, nres, diag_wg_count(nmax, sym));
 }
 
 // Queue the diagonal of one circuit; its C_max lands in result slot `res`.

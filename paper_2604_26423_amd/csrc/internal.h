@@ -275,6 +275,27 @@ hipError_t launch_cost_diagonal(int n, const int32_t *wmat_dev, int32_t *diag, i
                                 hipStream_t st, int sym = 0);
 int64_t diag_wg_count(int n, int sym = 0);
 
+// Scratch for building diagonals of up to nmax qubits with nwg workgroups of
+// the main kernel: the weight matrix (nmax x nmax int32), the low-bit table
+// (2^13 int32), per-workgroup maxima, their partial maxima and `nres` int32
+// results, each at a 256-byte aligned offset.
+struct DiagScratch {
+    size_t off_low, off_wg, off_tmp, off_res, total;
+};
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr DiagScratch diag_scratch_plan(int nmax, int nres, int64_t nwg)
+{
+    DiagScratch L{};
+    L.off_low = align256((size_t)nmax * nmax * 4);
+    L.off_wg = L.off_low + 8192 * 4;
+    L.off_tmp = L.off_wg + align256((size_t)nwg * 4);
+    L.off_res = L.off_tmp + align256((size_t)(nwg / 4096 + 2) * 4);
+    L.total = L.off_res + align256((size_t)nres * 4);
+    return L;
+}
+
 // Sampling.
 struct SampleBufs {
     uint64_t *sub;     // in-block exclusive prefix of 64-amplitude sub-block sums

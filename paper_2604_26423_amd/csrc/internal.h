@@ -8,10 +8,7 @@
 namespace qs {
 
 constexpr int kThreads = 256;         // threads per workgroup of the elementwise kernels
-#ifndef QS_FWD_TB
-#define QS_FWD_TB 8
-#endif
-constexpr int kFwdThreadBits = QS_FWD_TB; // forward tile kernels: 256 threads
+constexpr int kFwdThreadBits = 8;     // forward tile kernels: 256 threads
 constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128

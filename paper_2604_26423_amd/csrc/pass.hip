@@ -7,13 +7,7 @@
 // kernels in tangent form do the same, two workgroups per CU; the others run
 // one persistent workgroup per CU that loads the next tile's vectors into
 // registers while it works on the current tile (see adjoint_variant).
-#include <stdlib.h>
-
 #include "tiles.h"
-
-#ifndef QS_ADJ_PREFETCH
-#define QS_ADJ_PREFETCH 1
-#endif
 
 namespace qs {
 
@@ -54,7 +48,7 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
     using Cfg = TileCfg<V, T, TB>;
     constexpr int NT = Cfg::NT, NR = Cfg::NR;
     constexpr bool PAIR = !ONE;
-    constexpr bool PREFETCH = QS_ADJ_PREFETCH && !ONE;
+    constexpr bool PREFETCH = !ONE;
     static_assert(TB == 9, "exchange2 assumes 512-thread tiles");
     __shared__ V lds[(PAIR ? 2 : 1) << T];
     __shared__ V tab[kTabMax];
@@ -182,21 +176,10 @@ void launch_pass_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 // stage), a junction (stage, phase, stage) and the last pass (stage and
 // readout); anything else uses the runtime-shape kernel.  (A plain stage was
 // measured 1 ms slower fixed than with the runtime shape at n = 32.)
-// QS_PASS_SHAPES=0 in the environment selects the runtime-shape kernels
-// everywhere (for comparisons).
-int shapes_enabled()
-{
-    static const int on = [] {
-        const char *v = getenv("QS_PASS_SHAPES");
-        return v && v[0] == '0' ? 0 : 1;
-    }();
-    return on;
-}
-
 template <int MODE>
 void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
-    switch (shapes_enabled() ? pass_shape(pp) : -1) {
+    switch (pass_shape(pp)) {
     case kShInit | kShPhase | kShPost: launch_pass_s<MODE, kShInit | kShPhase | kShPost>(prec, pp, grid, st); break;
     case kShPre | kShPhase | kShPost: launch_pass_s<MODE, kShPre | kShPhase | kShPost>(prec, pp, grid, st); break;
     case kShPost | kShReadout: launch_pass_s<MODE, kShPost | kShReadout>(prec, pp, grid, st); break;
@@ -220,19 +203,14 @@ void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st
 // forward pass (phase of layer 1, no writes) and the reverse junction (stage,
 // phase, stage; its diagonal is loaded at the phase point).  The turnaround
 // and the junction are one-tile for complex64 only: in complex128 they spill
-// at 128 registers.  QS_ADJ_ONE_TILE=0 in the environment selects
-// kAdjPersistent everywhere (for comparisons).
+// at 128 registers.
 enum { kAdjPersistent, kAdjOneTurn, kAdjOnePlain, kAdjOneFirst, kAdjOneJunc };
 
 int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
 {
-    static const int on = [] {
-        const char *v = getenv("QS_ADJ_ONE_TILE");
-        return v && v[0] == '0' ? 0 : 1;
-    }();
-    if (!on || mode == kModeGeneral) return kAdjPersistent;
+    if (mode == kModeGeneral) return kAdjPersistent;
     if (turnaround) return prec == 0 ? kAdjOneTurn : kAdjPersistent;
-    switch (shapes_enabled() ? pass_shape(pp) : -1) {
+    switch (pass_shape(pp)) {
     case kShPost: return kAdjOnePlain;
     case kShInit | kShPhase | kShPost: return kAdjOneFirst;
     case kShPre | kShPhase | kShPost: return prec == 0 ? kAdjOneJunc : kAdjPersistent;

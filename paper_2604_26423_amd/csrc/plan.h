@@ -4,7 +4,6 @@
 #pragma once
 
 #include <stdint.h>
-#include <stdlib.h>
 
 #include <algorithm>
 #include <vector>
@@ -22,11 +21,8 @@ struct PassGeom {
 inline int cmin_for(int prec)
 {
     // Minimum carrier bits of a strided pass: contiguous runs of 2^c amplitudes
-    // (complex64: 8 x 8 B = 64 B; complex128: 8 x 16 B = 128 B).  The
-    // environment variable QS_CARRIER_BITS overrides it for tuning.
-    const char *v = getenv("QS_CARRIER_BITS");
-    const int env = v ? atoi(v) : 0;
-    if (env >= 1 && env <= tile_bits(prec) - 1) return env;
+    // (complex64: 8 x 8 B = 64 B; complex128: 8 x 16 B = 128 B).
+    (void)prec;
     return 3;
 }
 

@@ -264,6 +264,7 @@ extern "C" int qs_plan_check(int n, int prec_arg, int p, char *msg, size_t msg_l
             WinSeq seq[3];
             seq[0] = plan_windows(tb, g.targets, T, tb);                         // single stage
             seq[1] = plan_windows(tb, g.targets, T, tb);                         // pre stage
+            if (seq[1].cnt > kMaxWindows) return R.fail("pre stage: too many windows");
             seq[2] = plan_windows(seq[1].s[seq[1].cnt - 1], g.targets, T, tb);   // post stage after pre
             if (check_windows(R, seq[0], g.targets, 0u, T, tb, "single stage")) return 1;
             if (check_windows(R, seq[2], g.targets, 0u, T, tb, "post stage")) return 1;

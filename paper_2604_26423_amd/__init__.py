@@ -6,8 +6,8 @@ Nothing here falls back to a CPU implementation: without the built library
 every call raises.
 """
 from . import qs  # noqa: F401
-from .lrqaoa import (Batch, Simulator, Trajectories, expect_c, fit_k0, gate_grad_to_schedule, linear_ramp,  # noqa: F401
-                     mean_of_means, overlap_ratio, to_gate_angles)
+from .lrqaoa import (Batch, Simulator, Trajectories, expect_c, gate_grad_to_schedule, linear_ramp,  # noqa: F401
+                     mean_of_means, to_gate_angles)
 
 __all__ = ["qs", "Batch", "Simulator", "Trajectories", "expect_c", "linear_ramp", "to_gate_angles",
-           "gate_grad_to_schedule", "mean_of_means", "overlap_ratio", "fit_k0"]
+           "gate_grad_to_schedule", "mean_of_means"]

@@ -395,17 +395,3 @@ class Trajectories:
         except Exception:
             pass
 
-
-def overlap_ratio(r_noisy, r_ideal: float, r_random: float):
-    """r_ovl = (r_QPU - r_random) / (r_ideal - r_random) (Sec. II-C)."""
-    return (np.asarray(r_noisy, dtype=np.float64) - r_random) / (r_ideal - r_random)
-
-
-def fit_k0(eps_acc, r_ovl) -> float:
-    """Least-squares k0 of r_ovl = 2^(-k0 eps_acc) (Sec. II-C), fitted on
-    log2 r_ovl through the origin over the points with r_ovl > 0."""
-    x = np.asarray(eps_acc, dtype=np.float64)
-    y = np.asarray(r_ovl, dtype=np.float64)
-    keep = y > 0
-    x, ly = x[keep], np.log2(y[keep])
-    return float(-(x @ ly) / (x @ x))

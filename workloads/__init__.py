@@ -111,8 +111,3 @@ class NoiseRun:
 
 # throughput shape: the paper's largest noisy size, 10 layers, many trajectories
 NOISE_BENCH = NoiseRun("K12_p10_eps0.003", n=12, seed=2, p=10, delta=0.6, eps=0.003, ntraj=65536)
-# overlap study (Fig. 1b): sizes 8, 10, 12 (graph seed 100 + n), depths, rates
-NOISE_STUDY_N = (8, 10, 12)
-NOISE_STUDY_P = (3, 5, 10)
-NOISE_STUDY_EPS = (1e-4, 3e-4, 1e-3, 3e-3, 1e-2, 3e-2)
-NOISE_STUDY_TRAJ = 4096

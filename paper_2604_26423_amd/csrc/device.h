@@ -235,26 +235,30 @@ __device__ __forceinline__ void stage_rx(V (&v)[NR], uint32_t mask, uint32_t pma
     }
 }
 
-// Im <lam| X_q |psi> restricted to the pairs held in registers, for register bit K:
-// sum over pairs of Im(conj(l0) p1) + Im(conj(l1) p0), accumulated in FP64.
-// The pair terms of one register bit (NR/2 pairs held by the thread) are
-// summed in the state precision; the result joins an FP64 accumulator.
+// The gradient term of one amplitude pair (a0, a1) of a factor:
+// Im(conj(l0) p1) + Im(conj(l1) p0), a four-product dot in the state
+// precision (one fused multiply-add per product after the first).
+template <typename V>
+__device__ __forceinline__ typename Real<V>::T imx_pair(V l0, V l1, V p0, V p1)
+{
+    typename Real<V>::T t = l0.x * p1.y;
+    t = fma(-l0.y, p1.x, t);
+    t = fma(l1.x, p0.y, t);
+    return fma(-l1.y, p0.x, t);
+}
+
+// Im <lam| X_q |psi> restricted to the pairs held in registers, for register
+// bit K: the sum over the thread's NR/2 pairs of their terms.  Each pair's
+// term is formed in the state precision and the sum over pairs is taken in
+// FP64.
 template <int K, typename V, int NR>
 __device__ __forceinline__ double imx_reg_bit(const V (&l)[NR], const V (&p)[NR])
 {
-    using R = typename Real<V>::T;
-    R acc = 0;
+    double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        if (!(r & (1 << K))) {
-            const V l0 = l[r], l1 = l[r | (1 << K)], p0 = p[r], p1 = p[r | (1 << K)];
-            // one fused multiply-add per product
-            acc = fma(l0.x, p1.y, acc);
-            acc = fma(-l0.y, p1.x, acc);
-            acc = fma(l1.x, p0.y, acc);
-            acc = fma(-l1.y, p0.x, acc);
-        }
-    return (double)acc;
+        if (!(r & (1 << K))) acc += (double)imx_pair(l[r], l[r | (1 << K)], p[r], p[r | (1 << K)]);
+    return acc;
 }
 
 template <typename V, int NR>
@@ -304,19 +308,11 @@ __device__ __forceinline__ double imx_reg_ends(const V (&l)[NR], const V (&p)[NR
 template <int K, typename V, int NR>
 __device__ __forceinline__ double imx_reg_bit2(const V (&l)[NR], const V (&p)[NR])
 {
-    using R = typename Real<V>::T;
-    R acc = 0;
+    double acc = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r)
-        if (!(r & (1 << K))) {
-            const int q = r ^ (3 << K);
-            const V l0 = l[r], l1 = l[q], p0 = p[r], p1 = p[q];
-            acc = fma(l0.x, p1.y, acc);
-            acc = fma(-l0.y, p1.x, acc);
-            acc = fma(l1.x, p0.y, acc);
-            acc = fma(-l1.y, p0.x, acc);
-        }
-    return (double)acc;
+        if (!(r & (1 << K))) acc += (double)imx_pair(l[r], l[r ^ (3 << K)], p[r], p[r ^ (3 << K)]);
+    return acc;
 }
 
 template <typename V, int NR>

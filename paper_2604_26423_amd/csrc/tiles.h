@@ -487,17 +487,20 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     }
     if (has_phase) {
         if constexpr (LATE) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
-        R gz = 0;  // sum of C Im(conj(l) p) over the thread's amplitudes
+        // sum of C Im(conj(l) p) over the thread's amplitudes: each
+        // amplitude's Im(conj(l) p) in the state precision, the products with
+        // C and their sum in FP64
+        double gz = 0.0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             R im = l[r].x * p[r].y;
             im = fma(-l[r].y, p[r].x, im);
-            gz = fma((R)dg[r], im, gz);
+            gz = fma((double)dg[r], (double)im, gz);
         }
         // pin the sum here: sunk past the next stage, it would keep the
         // vectors' values at the phase point live through that stage
         asm volatile("" : "+v"(gz));
-        acc[1] += -0.2 * (double)gz * (fold && has_post ? pp.fpost * pp.fpost : 1.0);
+        acc[1] += -0.2 * gz * (fold && has_post ? pp.fpost * pp.fpost : 1.0);
         if (!init) unphase_quarters(tab, pp.phase_levels, dg, p, l);
     }
     if (has_pre) {

@@ -92,3 +92,54 @@ def test_full_uneven_batch():
         assert abs(e[i] - es) <= 2e-5 * es
         assert np.abs(gzz[i] - szz).max() <= 1e-4 * scale and np.abs(gx[i] - sx).max() <= 1e-4 * scale
     b.close()
+
+
+def test_full_batch_c128_vs_oracle_and_c64_vs_c128():
+    """The 512-circuit workload in both precisions.  The complex128 batch is
+    pinned to the FP64 oracle on 36 circuits, four of each size n = 14..22
+    (<C> from the oracle's state, the gradient from its gate-by-gate adjoint
+    on the smallest-depth circuit of each size), which covers every pass
+    geometry of the batch (8 down to 4 carrier bits).  Every complex64
+    circuit is then held to the complex128 one: <C> within 1e-6 relative and
+    the gradient within 1e-4 of its largest component."""
+    from paper_2604_26423_amd import Batch
+    items = workloads.batch()
+    inst = [(it.weights(), it.p) for it in items]
+    ang = [oracle.gate_angles(*oracle.ramp_midpoint(it.p, it.delta_gamma, it.delta_beta)) for it in items]
+    out = {}
+    for prec in ("c128", "c64"):
+        say(f"512-circuit batch, {prec}")
+        b = Batch(inst, prec)
+        out[prec] = b.forward_grad([a[0] for a in ang], [a[1] for a in ang])
+        cmax = list(b.cmax)
+        b.close()
+    e128, gzz128, gx128 = out["c128"]
+    picked = []
+    for n in range(14, 23):
+        of_n = [i for i, it in enumerate(items) if it.n == n]
+        assert len(of_n) >= 4, n
+        picked += of_n[:4]
+        i = min(of_n, key=lambda j: items[j].p)
+        say(f"  oracle adjoint: circuit {i}, n={n}, p={items[i].p}")
+        er, rzz, rx = oracle.adjoint(n, inst[i][0], *ang[i])
+        sc = max(np.abs(rzz).max(), np.abs(rx).max())
+        assert abs(e128[i] - er) <= 1e-12 * er
+        assert np.abs(gzz128[i] - rzz).max() <= 1e-10 * sc and np.abs(gx128[i] - rx).max() <= 1e-10 * sc
+    for i in picked:
+        it = items[i]
+        ref = oracle.simulate(it.n, inst[i][0], *ang[i], mode=1)
+        er, _ = oracle.expect(ref, oracle.cost_diagonal(it.n, inst[i][0]))
+        assert abs(e128[i] - er) <= 1e-12 * er, (i, it.n, e128[i], er)
+        assert cmax[i] == oracle.cmax_direct(it.n, inst[i][0])
+    e64, gzz64, gx64 = out["c64"]
+    e_err = np.abs(np.asarray(e64) - np.asarray(e128)) / np.asarray(e128)
+    g_err = np.array([max(np.abs(a - c).max(), np.abs(b - d).max()) / max(np.abs(c).max(), np.abs(d).max())
+                      for a, b, c, d in zip(gzz64, gx64, gzz128, gx128)])
+    say(f"  complex64 vs complex128 over 512 circuits: <C> max {e_err.max():.2e} median {np.median(e_err):.2e}; "
+        f"gradient max {g_err.max():.2e} median {np.median(g_err):.2e}")
+    for i in np.argsort(g_err)[-3:]:
+        it = items[i]
+        say(f"    circuit {i}: n={it.n} p={it.p} D=({it.delta_gamma:.3f}, {it.delta_beta:.3f}) gradient error "
+            f"{g_err[i]:.2e}, largest component {max(np.abs(gzz128[i]).max(), np.abs(gx128[i]).max()):.3e}")
+    assert e_err.max() <= 1e-6
+    assert g_err.max() <= 1e-4

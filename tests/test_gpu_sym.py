@@ -32,12 +32,15 @@ def half_of_int(n, a):
 CASES = [(14, 1), (14, 3), (15, 2), (16, 3), (18, 4), (20, 3), (22, 2)]
 
 
-@pytest.mark.parametrize("precision", ["c64", "c128"])
-@pytest.mark.parametrize("n,p", CASES)
+def with_precisions(cases):
+    """Each case in both precisions, except complex64 below n = 15 (the
+    complex64 half-state layout needs n >= 15)."""
+    return [(*c, prec) for prec in ("c64", "c128") for c in cases if not (prec == "c64" and c[0] < 15)]
+
+
+@pytest.mark.parametrize("n,p,precision", with_precisions(CASES))
 def test_sym_forward_vs_oracle(n, p, precision):
     from paper_2604_26423_amd import Simulator
-    if precision == "c64" and n < 15:
-        pytest.skip("complex64 symmetric layout needs n >= 15")
     say(f"sym forward n={n} p={p} {precision}")
     w = workloads.complete_graph_tenths(n, 500 + n)
     s = Simulator(w, precision, symmetric=True)
@@ -76,12 +79,11 @@ def test_sym_separate_ops(precision):
     s.close()
 
 
-@pytest.mark.parametrize("precision", ["c64", "c128"])
-@pytest.mark.parametrize("n,shots", [(15, 5000), (20, 20000), (28, 30000)])
+# one precision is enough for the multi-chunk case (n = 28)
+@pytest.mark.parametrize("n,shots,precision", [(15, 5000, "c64"), (20, 20000, "c64"), (28, 30000, "c64"),
+                                               (15, 5000, "c128"), (20, 20000, "c128")])
 def test_sym_sampling_bit_exact_on_same_state(n, shots, precision):
     from paper_2604_26423_amd import Simulator
-    if n == 28 and precision == "c128":
-        pytest.skip("one precision is enough for the multi-chunk case")
     say(f"sym sampling n={n} {precision}")
     w = workloads.complete_graph_tenths(n, 60 + n)
     s = Simulator(w, precision, symmetric=True)
@@ -109,12 +111,9 @@ def test_sym_histogram_equals_full(precision):
     s.close()
 
 
-@pytest.mark.parametrize("precision", ["c64", "c128"])
-@pytest.mark.parametrize("n,p", [(14, 2), (16, 3), (19, 2)])
+@pytest.mark.parametrize("n,p,precision", with_precisions([(14, 2), (16, 3), (19, 2)]))
 def test_sym_adjoint_vs_oracle(n, p, precision):
     from paper_2604_26423_amd import Simulator
-    if precision == "c64" and n < 15:
-        pytest.skip("complex64 symmetric layout needs n >= 15")
     say(f"sym adjoint n={n} p={p} {precision}")
     w = workloads.complete_graph_tenths(n, 70 + n)
     tzz, tx = angles(p, n + 1)

@@ -136,6 +136,124 @@ __global__ void __launch_bounds__(1 << kFwdThreadBits) tile_probe_kernel(f2 *psi
     }
 }
 
+// ---- mixer-window microbenchmark: butterflies against FP32 matrix cores ----
+// Both kernels multiply every group of 16 consecutive amplitudes of two
+// complex64 vectors by K = (x)^4 [[1, -iu], [-iu, 1]] (the tangent-form RX of
+// one four-qubit register window), `windows` times per load.
+constexpr float kWinU = 0.25f;
+
+__global__ void __launch_bounds__(256) window_valu_kernel(float2 *a, float2 *b, int windows)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;  // one group per thread
+    f4 *pa = reinterpret_cast<f4 *>(a + g * 16), *pb = reinterpret_cast<f4 *>(b + g * 16);
+    float2 x[16], y[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const f4 u = pa[i], v = pb[i];
+        x[2 * i] = float2{u.x, u.y};
+        x[2 * i + 1] = float2{u.z, u.w};
+        y[2 * i] = float2{v.x, v.y};
+        y[2 * i + 1] = float2{v.z, v.w};
+    }
+#pragma unroll 1
+    for (int w = 0; w < windows; ++w) {
+        rxt_reg_bit<0>(x, kWinU);
+        rxt_reg_bit<1>(x, kWinU);
+        rxt_reg_bit<2>(x, kWinU);
+        rxt_reg_bit<3>(x, kWinU);
+        rxt_reg_bit<0>(y, kWinU);
+        rxt_reg_bit<1>(y, kWinU);
+        rxt_reg_bit<2>(y, kWinU);
+        rxt_reg_bit<3>(y, kWinU);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        pa[i] = f4{x[2 * i].x, x[2 * i].y, x[2 * i + 1].x, x[2 * i + 1].y};
+        pb[i] = f4{y[2 * i].x, y[2 * i].y, y[2 * i + 1].x, y[2 * i + 1].y};
+    }
+}
+
+// Multiply by i^k (k mod 4).
+__device__ __forceinline__ float2 rot_i(float2 v, int k)
+{
+    switch (k & 3) {
+    case 0: return v;
+    case 1: return float2{-v.y, v.x};
+    case 2: return float2{-v.x, -v.y};
+    default: return float2{v.y, -v.x};
+    }
+}
+
+// v_mfma_f32_16x16x4f32 (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and receives D[4 (l / 16) + i][l % 16], i = 0..3.  A wave
+// takes 16 groups as the columns of a 16 x 16 matrix X; lane (j = l / 16,
+// c = l % 16) holds rows 4j .. 4j + 3 of column c, the layout of D, so the
+// product can be fed back.  The K = 16 sum runs as four slices s, in which
+// lane (j, c) supplies B = X[4j + s][c] (its own s-th row) and A = M[c][4j + s],
+// with M = D K D^-1, M[r][q] = (-1)^|q & ~r| u^|r ^ q|, D = diag(i^|r|).
+__global__ void __launch_bounds__(256) window_mfma_kernel(float2 *a, float2 *b, int windows)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane >> 4, c = lane & 15;
+    const int64_t g = ((int64_t)blockIdx.x * 4 + wave) * 16 + c;  // this lane's group
+    f4 *pa = reinterpret_cast<f4 *>(a + g * 16 + 4 * j), *pb = reinterpret_cast<f4 *>(b + g * 16 + 4 * j);
+    float am[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int q = 4 * j + s;
+        float m = 1.0f;
+        for (int t = __builtin_popcount(c ^ q); t > 0; --t) m *= kWinU;
+        am[s] = (__builtin_popcount(q & ~c) & 1) ? -m : m;
+    }
+    float2 x[4], y[4];
+    {
+        const f4 u0 = pa[0], u1 = pa[1], v0 = pb[0], v1 = pb[1];
+        x[0] = float2{u0.x, u0.y};
+        x[1] = float2{u0.z, u0.w};
+        x[2] = float2{u1.x, u1.y};
+        x[3] = float2{u1.z, u1.w};
+        y[0] = float2{v0.x, v0.y};
+        y[1] = float2{v0.z, v0.w};
+        y[2] = float2{v1.x, v1.y};
+        y[3] = float2{v1.z, v1.w};
+    }
+    f4 xr, xi, yr, yi;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = __builtin_popcount(4 * j + i);
+        const float2 p = rot_i(x[i], k), q = rot_i(y[i], k);
+        xr[i] = p.x;
+        xi[i] = p.y;
+        yr[i] = q.x;
+        yi[i] = q.y;
+    }
+#pragma unroll 1
+    for (int w = 0; w < windows; ++w) {
+        f4 nxr{0.f, 0.f, 0.f, 0.f}, nxi = nxr, nyr = nxr, nyi = nxr;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            nxr = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], xr[s], nxr, 0, 0, 0);
+            nxi = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], xi[s], nxi, 0, 0, 0);
+            nyr = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], yr[s], nyr, 0, 0, 0);
+            nyi = __builtin_amdgcn_mfma_f32_16x16x4f32(am[s], yi[s], nyi, 0, 0, 0);
+        }
+        xr = nxr;
+        xi = nxi;
+        yr = nyr;
+        yi = nyi;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 - __builtin_popcount(4 * j + i);
+        x[i] = rot_i(float2{xr[i], xi[i]}, k);
+        y[i] = rot_i(float2{yr[i], yi[i]}, k);
+    }
+    pa[0] = f4{x[0].x, x[0].y, x[1].x, x[1].y};
+    pa[1] = f4{x[2].x, x[2].y, x[3].x, x[3].y};
+    pb[0] = f4{y[0].x, y[0].y, y[1].x, y[1].y};
+    pb[1] = f4{y[2].x, y[2].y, y[3].x, y[3].y};
+}
+
 template <int KIND, int U, bool NTL, bool NTS>
 void launch_stream_u(f4 *a, const f4 *b, const i2 *ph, int64_t nchunks, int64_t grid, float s, hipStream_t st)
 {
@@ -170,6 +288,16 @@ void launch_stream_f(int kind, int U, f4 *a, const f4 *b, const i2 *ph, int64_t 
 void launch_probe(const qs_probe &pr, void *a, const void *b, size_t bytes, int64_t cus, float s, hipStream_t st)
 {
     const bool ntl = (pr.flags & QS_PROBE_NT_LOAD) != 0, nts = (pr.flags & QS_PROBE_NT_STORE) != 0;
+    if (pr.kind == QS_PROBE_WINDOW_VALU) {  // 256 groups of 16 amplitudes per workgroup
+        hipLaunchKernelGGL(window_valu_kernel, dim3((unsigned)((int64_t)1 << (pr.n - 12))), dim3(256), 0, st,
+                           (float2 *)a, (float2 *)b, pr.windows);
+        return;
+    }
+    if (pr.kind == QS_PROBE_WINDOW_MFMA) {  // 64 groups per workgroup
+        hipLaunchKernelGGL(window_mfma_kernel, dim3((unsigned)((int64_t)1 << (pr.n - 10))), dim3(256), 0, st,
+                           (float2 *)a, (float2 *)b, pr.windows);
+        return;
+    }
     if (pr.kind == QS_PROBE_TILE) {
         const int64_t ntiles = (int64_t)1 << (pr.n - kTileBitsC64);
         const int xcd = ntiles % 8 == 0 ? 1 : 0;
@@ -208,13 +336,23 @@ extern "C" qs_status qs_bandwidth_probe(const qs_probe *pr, void *a, const void 
                                         void *hip_stream, double *ms_per_launch, double *bytes_per_launch)
 {
     if (!pr) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: null probe");
-    if (pr->kind < QS_PROBE_READ || pr->kind > QS_PROBE_TILE) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: bad kind");
+    if (pr->kind < QS_PROBE_READ || pr->kind > QS_PROBE_WINDOW_MFMA)
+        return set_error(QS_ERR_ARG, "qs_bandwidth_probe: bad kind");
     if (pr->flags & ~(QS_PROBE_NT_LOAD | QS_PROBE_NT_STORE)) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: bad flags");
     if (pr->wg_per_cu < 0 || pr->wg_per_cu > 64) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: wg_per_cu outside 0..64");
     if (reps < 1 || reps > 1000) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: reps outside 1..1000");
     if (!a || ((uintptr_t)a & 255)) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: a must be a 256-byte aligned buffer");
     double moved = 0.0;
-    if (pr->kind == QS_PROBE_TILE) {
+    if (pr->kind == QS_PROBE_WINDOW_VALU || pr->kind == QS_PROBE_WINDOW_MFMA) {
+        if (pr->n < 12 || pr->n > QS_MAX_QUBITS_C64)
+            return set_error(QS_ERR_ARG, "qs_bandwidth_probe: window probe needs 12 <= n <= 34");
+        if (pr->windows < 1 || pr->windows > 64)
+            return set_error(QS_ERR_ARG, "qs_bandwidth_probe: windows outside 1..64");
+        if (bytes != ((size_t)8 << pr->n)) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: window probe needs bytes = 2^n * 8");
+        if (!b || ((uintptr_t)b & 255)) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: b must be a 256-byte aligned buffer");
+        if (pr->flags) return set_error(QS_ERR_ARG, "qs_bandwidth_probe: window probes take no flags");
+        moved = 4.0 * (double)bytes;
+    } else if (pr->kind == QS_PROBE_TILE) {
         if (pr->n < kTileBitsC64 + 1 || pr->n > QS_MAX_QUBITS_C64)
             return set_error(QS_ERR_ARG, "qs_bandwidth_probe: tile probe needs 14 <= n <= 34");
         const int m = kTileBitsC64 - pr->c;

@@ -52,16 +52,19 @@ class QSCircuit(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("p", ctypes.c_int), ("w_tenths", ctypes.c_void_p)]
 
 
-(QS_PROBE_READ, QS_PROBE_WRITE, QS_PROBE_COPY, QS_PROBE_UPDATE, QS_PROBE_PHASE, QS_PROBE_TILE) = range(6)
+(QS_PROBE_READ, QS_PROBE_WRITE, QS_PROBE_COPY, QS_PROBE_UPDATE, QS_PROBE_PHASE, QS_PROBE_TILE,
+ QS_PROBE_WINDOW_VALU, QS_PROBE_WINDOW_MFMA) = range(8)
 PROBE_KINDS = {"read": QS_PROBE_READ, "write": QS_PROBE_WRITE, "copy": QS_PROBE_COPY, "update": QS_PROBE_UPDATE,
-               "phase": QS_PROBE_PHASE, "tile": QS_PROBE_TILE}
+               "phase": QS_PROBE_PHASE, "tile": QS_PROBE_TILE, "window_valu": QS_PROBE_WINDOW_VALU,
+               "window_mfma": QS_PROBE_WINDOW_MFMA}
+PROBE_WINDOW_U = 0.25   # u = tan(theta / 2) of the window probes
 QS_PROBE_NT_LOAD, QS_PROBE_NT_STORE = 1, 2
 
 
 class QSProbe(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("flags", ctypes.c_int), ("wg_per_cu", ctypes.c_int),
                 ("unroll", ctypes.c_int), ("n", ctypes.c_int), ("c", ctypes.c_int), ("q0", ctypes.c_int),
-                ("swizzle", ctypes.c_int)]
+                ("swizzle", ctypes.c_int), ("windows", ctypes.c_int)]
 
 
 class QSError(RuntimeError):
@@ -437,10 +440,11 @@ def qs_noise_free(h) -> None:
 
 
 def qs_bandwidth_probe(kind: int, a, b=None, nbytes: int = 0, reps: int = 5, flags: int = 0, wg_per_cu: int = 0,
-                       unroll: int = 0, n: int = 0, c: int = 0, q0: int = 0, swizzle: int = 1,
+                       unroll: int = 0, n: int = 0, c: int = 0, q0: int = 0, swizzle: int = 1, windows: int = 1,
                        stream=None) -> tuple:
-    """(ms per launch, bytes read + written per launch) of a data-movement probe (include/qs_probe.h)."""
-    pr = QSProbe(int(kind), int(flags), int(wg_per_cu), int(unroll), int(n), int(c), int(q0), int(swizzle))
+    """(ms per launch, bytes read + written per launch) of a probe kernel (include/qs_probe.h)."""
+    pr = QSProbe(int(kind), int(flags), int(wg_per_cu), int(unroll), int(n), int(c), int(q0), int(swizzle),
+                 int(windows))
     ms, by = ctypes.c_double(), ctypes.c_double()
     _check(lib().qs_bandwidth_probe(ctypes.byref(pr), _ptr(a), _ptr(b), int(nbytes), int(reps), _stream(stream),
                                     ctypes.byref(ms), ctypes.byref(by)))

@@ -264,6 +264,13 @@ def test_bandwidth_probe_validation():
     expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB + 16)       # size
     expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_COPY, FAKE, FAKE, MiB, unroll=3)
     expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 20, n=20, c=3, q0=13)  # bytes != 2^n * 8
+    for kind in (qs.QS_PROBE_WINDOW_VALU, qs.QS_PROBE_WINDOW_MFMA):
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, FAKE, 8 << 20, n=21, windows=1)      # bytes != 2^n * 8
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, FAKE, 8 << 11, n=11, windows=1)      # n < 12
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, FAKE, 8 << 20, n=20, windows=0)
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, FAKE, 8 << 20, n=20, windows=65)
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, None, 8 << 20, n=20, windows=4)      # needs b
+        expect_status(qs.QS_ERR_ARG, P, kind, FAKE, FAKE, 8 << 20, n=20, windows=4, flags=1)
     expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 20, n=20, c=3, q0=11)  # tile beyond n
     expect_status(qs.QS_ERR_ARG, P, qs.QS_PROBE_TILE, FAKE, None, 8 << 13, n=13, c=0, q0=0)   # n too small
     expect_status(qs.QS_ERR_HIP, P, qs.QS_PROBE_WRITE, FAKE, None, MiB)

@@ -255,6 +255,7 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     pp.W = cc.W;
     pp.phase_levels = phase_table_levels(cc.W);
     pp.amp0 = sqrt(ldexp(1.0, -(n + sym)));
+    pp.lam_shift = 0.5 * (double)cc.W;
     return pp;
 }
 
@@ -457,6 +458,7 @@ qs_status run_small_adjoint(qs_state s, const Circuit &cc, void *lam, const char
         sp.turnaround = (ch == nch - 1) ? 1 : 0;
         sp.store = 1;
         sp.amp0 = sqrt(ldexp(1.0, -s->n));
+        sp.lam_shift = 0.5 * (double)cc.W;
         Launch L(s, QS_KIND_SMALL, ldexp(1.0, s->n) * amp_bytes(s->prec) * 4);
         HIPCHK(launch_small_adjoint(s->prec, sp, s->stream), where);
         L.done();

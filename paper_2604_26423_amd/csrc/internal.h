@@ -69,6 +69,9 @@ struct PassProg {
     int64_t W;            // W_t
     int phase_levels;     // digits of the phase table (see pass.hip)
     double amp0;          // 2^(-n/2)
+    double lam_shift;     // adjoint: c (tenths) in lambda = (C - c) psi / 10 at the turnaround and in
+                          // the weights (C - c) of the phase gradients; any c gives the same
+                          // gradients, c = W_t / 2 keeps the terms small (see tiles.h)
 };
 
 // ---- index maps of a tile pass (host and device) ----
@@ -217,9 +220,10 @@ struct SmallProg {
     int do_mixer[kSmallMaxLayers];
     int layer0;           // index of the first layer of the chunk (gradient slots)
     int ptotal;           // total layers of the circuit (gradient slot layout)
-    int turnaround;       // adjoint: build lambda = C psi from the loaded psi first
+    int turnaround;       // adjoint: build lambda = (C - lam_shift) psi / 10 from the loaded psi first
     int store;            // adjoint: write psi and lambda back
     double amp0;          // 2^(-n/2)
+    double lam_shift;     // adjoint: shift of the cost in lambda and in the phase-gradient weights (tenths)
 };
 hipError_t launch_small_forward(int prec, const SmallProg &sp, hipStream_t st);
 hipError_t launch_small_adjoint(int prec, const SmallProg &sp, hipStream_t st);

@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(kSmallThreads) small_adjoint(SmallProg sp)
             const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
             acc[0] += pr;
             acc[1] += pr * (double)sp.diag[x];
-            const R cu = (R)((double)sp.diag[x] * 0.1);
+            const R cu = (R)(((double)sp.diag[x] - sp.lam_shift) * 0.1);
             sl_[x] = V{cu * a.x, cu * a.y};
         }
         block_sum(acc, red, tid, kSmallThreads);
@@ -146,7 +146,8 @@ __global__ void __launch_bounds__(kSmallThreads) small_adjoint(SmallProg sp)
             double acc[1] = {0.0};
             for (int x = tid; x < dim; x += kSmallThreads) {
                 const V l0 = sl_[x], p0 = sp_[x];
-                acc[0] += -0.2 * (double)sp.diag[x] * ((double)l0.x * (double)p0.y - (double)l0.y * (double)p0.x);
+                acc[0] += -0.2 * ((double)sp.diag[x] - sp.lam_shift) *
+                          ((double)l0.x * (double)p0.y - (double)l0.y * (double)p0.x);
             }
             block_sum(acc, red, tid, kSmallThreads);
             if (tid == 0) sp.out[2 + k] += acc[0];

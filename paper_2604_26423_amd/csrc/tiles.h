@@ -349,8 +349,19 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
 }
 
 // Turnaround on one tile: apply the last forward pass, read out the norm and
-// sum |a|^2 C_t (acc[1], acc[2]), form lambda = C psi, undo the pass on both
-// vectors (acc[0] += gx of the pass's layer) and store lambda only.  Split
+// sum |a|^2 C_t (acc[1], acc[2]), form lambda = (C - c) psi (C and c in
+// weight units, c = pp.lam_shift / 10), undo the pass on both vectors
+// (acc[0] += gx of the pass's layer) and store lambda only.
+//
+// Any constant c gives the same gradients: the reverse sweep applies the same
+// unitaries to both vectors, so the c psi part of lambda adds
+// c Im <psi_k| X_q |psi_k> and c Im <psi_k| C |psi_k> to the mixer and cost
+// terms, and both vanish (<psi|X_q|psi> and <psi|C|psi> are real).  Likewise
+// the phase-gradient weights may be C - c for any c, since Im <lam_k|psi_k> =
+// Im <psi|(C - c)|psi> = 0.  With c = W_t / 2 (the mean cut over all
+// bitstrings) the terms, and with them the rounding of a complex64 sweep, are
+// several times smaller than with c = 0, where they are of the size of <C>
+// and cancel to a gradient of order 1.  Split
 // into loads (psi in the load layout, the diagonal in the final layout) and
 // the rest, so that a persistent kernel can load the next tile early.
 template <typename V, int T, int TB>
@@ -398,7 +409,7 @@ __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V
         const double pr = (double)p[r].x * (double)p[r].x + (double)p[r].y * (double)p[r].y;
         acc[1] += pr;
         acc[2] += pr * (double)C;
-        l[r] = scale_v(p[r], (R)((double)C * 0.1));
+        l[r] = scale_v(p[r], (R)(((double)C - pp.lam_shift) * 0.1));
     }
     unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
@@ -487,15 +498,16 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     }
     if (has_phase) {
         if constexpr (LATE) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
-        // sum of C Im(conj(l) p) over the thread's amplitudes: each
-        // amplitude's Im(conj(l) p) in the state precision, the products with
-        // C and their sum in FP64
+        // sum of (C - c) Im(conj(l) p) over the thread's amplitudes (c: see
+        // turn_compute): each amplitude's Im(conj(l) p) in the state
+        // precision, the products with C - c and their sum in FP64
+        const double cs = pp.lam_shift;
         double gz = 0.0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             R im = l[r].x * p[r].y;
             im = fma(-l[r].y, p[r].x, im);
-            gz = fma((double)dg[r], (double)im, gz);
+            gz = fma((double)dg[r] - cs, (double)im, gz);
         }
         // pin the sum here: sunk past the next stage, it would keep the
         // vectors' values at the phase point live through that stage

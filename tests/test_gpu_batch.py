@@ -100,8 +100,9 @@ def test_full_batch_c128_vs_oracle_and_c64_vs_c128():
     (<C> from the oracle's state, the gradient from its gate-by-gate adjoint
     on the smallest-depth circuit of each size), which covers every pass
     geometry of the batch (8 down to 4 carrier bits).  Every complex64
-    circuit is then held to the complex128 one: <C> within 1e-6 relative and
-    the gradient within 1e-4 of its largest component."""
+    circuit is then held to the complex128 one: <C> within 5e-7 relative and
+    the gradient within 3e-5 of its largest component (measured: 5.3e-8 and
+    2.4e-6 at most, medians 1.5e-9 and 2.9e-7)."""
     from paper_2604_26423_amd import Batch
     items = workloads.batch()
     inst = [(it.weights(), it.p) for it in items]
@@ -141,5 +142,5 @@ def test_full_batch_c128_vs_oracle_and_c64_vs_c128():
         it = items[i]
         say(f"    circuit {i}: n={it.n} p={it.p} D=({it.delta_gamma:.3f}, {it.delta_beta:.3f}) gradient error "
             f"{g_err[i]:.2e}, largest component {max(np.abs(gzz128[i]).max(), np.abs(gx128[i]).max()):.3e}")
-    assert e_err.max() <= 1e-6
-    assert g_err.max() <= 1e-4
+    assert e_err.max() <= 5e-7
+    assert g_err.max() <= 3e-5

@@ -279,7 +279,8 @@ def test_adjoint_c64_vs_oracle(n, p):
     err = max(np.abs(gzz - rzz).max(), np.abs(gx - rx).max()) / scale
     say(f"  c64 n={n}: <C> rel {abs(e - e_ref) / e_ref:.2e}, gradient rel {err:.2e}")
     assert abs(e - e_ref) <= 1e-6 * abs(e_ref)
-    assert err <= 1e-4
+    # measured 0.8e-7 .. 5.3e-7 over these cases
+    assert err <= 5e-6
     sim.close()
 
 

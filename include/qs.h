@@ -160,6 +160,20 @@ qs_status qs_cost_diagonal_sym(int n, const int32_t *w_tenths, int32_t *diag_dev
                                int64_t *w_total_tenths, int32_t *cmax_tenths, void *hip_stream);
 
 /*
+ * qs_cost_diagonal without any device allocation, for callers that cannot
+ * allocate: code that runs under stream capture or in tight serving loops,
+ * and harnesses that forbid hipMalloc.  Same arguments, outputs and errors as
+ * qs_cost_diagonal, for 1 <= n <= 34 (larger n: QS_ERR_ARG).  Its scratch is
+ * a static array in device memory (8.04 MiB; each device the library runs on
+ * holds its own copy until the process ends), shared by every call on that
+ * device: calls that overlapped on one device would race, so the library
+ * lets one call at a time use it (calls from several host threads wait for
+ * each other).  Synchronises hip_stream before it returns.
+ */
+qs_status qs_cost_diagonal_noalloc(int n, const int32_t *w_tenths, int32_t *diag_dev,
+                                   int64_t *w_total_tenths, int32_t *cmax_tenths, void *hip_stream);
+
+/*
  * One cost layer, eq. (2): prod_{i<j} RZZ(theta_zz * w_ij), applied as the
  * diagonal phase exp(-i theta_zz (W_t - 2 C_t[x]) / 20) on every amplitude.
  * The phase argument is reduced modulo 2 pi in FP64.

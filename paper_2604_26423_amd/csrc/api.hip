@@ -672,11 +672,12 @@ BatchSchedule build_batch_schedule(qs_batch b, const double *theta_zz, const dou
 
 // ---------------------------------------------------------------- diagonal helpers
 // Dense symmetric weight matrix from the lexicographic edge list, with checks.
-qs_status weight_matrix(int n, const int32_t *w, std::vector<int32_t> &wm, int64_t *W)
+// wm: n * n entries, filled (diagonal zero).
+qs_status weight_matrix(int n, const int32_t *w, int32_t *wm, int64_t *W)
 {
     const int64_t ne = (int64_t)n * (n - 1) / 2;
     if (ne > 0 && !w) return fail(QS_ERR_ARG, "null weight array");
-    wm.assign((size_t)n * n, 0);
+    for (int64_t i = 0; i < (int64_t)n * n; ++i) wm[i] = 0;
     int64_t sum = 0, e = 0;
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j, ++e) {
@@ -697,10 +698,10 @@ DiagScratch diag_scratch_layout(int nmax, int nres, int sym = 0)
 
 // Queue the diagonal of one circuit; its C_max lands in result slot `res`.
 // `wm` must stay alive until the stream has run the copy.
-hipError_t build_diagonal(int n, const std::vector<int32_t> &wm, int32_t *diag, char *scratch, const DiagScratch &L,
+hipError_t build_diagonal(int n, const int32_t *wm, int32_t *diag, char *scratch, const DiagScratch &L,
                           int res, hipStream_t st, int sym = 0)
 {
-    hipError_t e = hipMemcpyAsync(scratch, wm.data(), (size_t)n * n * 4, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(scratch, wm, (size_t)n * n * 4, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     return launch_cost_diagonal(n, (const int32_t *)scratch, diag, (int32_t *)(scratch + L.off_low),
                                 (int32_t *)(scratch + L.off_wg), (int32_t *)(scratch + L.off_tmp),
@@ -830,9 +831,9 @@ qs_status cost_diagonal_impl(int n, int sym, const int32_t *w_tenths, int32_t *d
     try {
         if (!diag_dev) return fail(QS_ERR_ARG, "null diagonal buffer");
         if (!aligned(diag_dev, 16)) return fail(QS_ERR_ARG, "diagonal buffer must be 16-byte aligned");
-        std::vector<int32_t> wm;
+        std::vector<int32_t> wm((size_t)n * n);
         int64_t W = 0;
-        if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
+        if (qs_status st = weight_matrix(n, w_tenths, wm.data(), &W)) return st;
         hipStream_t st = (hipStream_t)hip_stream;
         const DiagScratch L = diag_scratch_layout(n, 1, sym);
         int dev = 0;
@@ -841,7 +842,7 @@ qs_status cost_diagonal_impl(int n, int sym, const int32_t *w_tenths, int32_t *d
         std::lock_guard<std::mutex> lock(cache->mu);
         HIPCHK(cache->buf.ensure(L.total), "qs_cost_diagonal");
         char *scratch = (char *)cache->buf.p;
-        hipError_t he = build_diagonal(n, wm, diag_dev, scratch, L, 0, st, sym);
+        hipError_t he = build_diagonal(n, wm.data(), diag_dev, scratch, L, 0, st, sym);
         int32_t cmax = 0;
         if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch + L.off_res, 4, hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
@@ -868,6 +869,68 @@ qs_status qs_cost_diagonal_sym(int n, const int32_t *w_tenths, int32_t *diag_dev
     if (n < 14 || n > QS_MAX_QUBITS_C64 + 1)
         return fail(QS_ERR_ARG, "n = %d outside 14..%d", n, QS_MAX_QUBITS_C64 + 1);
     return cost_diagonal_impl(n, 1, w_tenths, diag_dev, w_total_tenths, cmax_tenths, hip_stream);
+}
+
+namespace {
+// Scratch of qs_cost_diagonal_noalloc, sized for the largest diagonal
+// (n = QS_MAX_QUBITS_C64: the weight matrix, the low-bit table, 2^21
+// per-workgroup maxima, their partial maxima and the result; 8.04 MiB).  A
+// static array in device memory: every device the library runs on holds its
+// own copy until the process ends.  Host code never names the array except in
+// the symbol lookup below; it passes the per-device address that lookup
+// returns.  Nothing in it needs to start at zero: every kernel writes each
+// word it later reads.
+constexpr DiagScratch kNoallocDiag =
+    diag_scratch_plan(QS_MAX_QUBITS_C64, 1, (int64_t)1 << (QS_MAX_QUBITS_C64 - kDiagLowBits));
+__device__ __align__(256) char noalloc_diag_scratch[kNoallocDiag.total];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;                  // held for a whole call: calls in one process take turns
+void *g_noalloc_ptr[kMaxDevices] = {};    // address of each device's copy, looked up once
+
+qs_status noalloc_scratch(char **out, const char *where)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev), where);
+    if (dev < 0 || dev >= kMaxDevices) return fail(QS_ERR_HIP, "%s: device %d beyond %d", where, dev, kMaxDevices);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_diag_scratch)), where);
+        if (!p) return fail(QS_ERR_HIP, "%s: no device address for the scratch array", where);
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = (char *)g_noalloc_ptr[dev];
+    return QS_OK;
+}
+}  // namespace
+
+qs_status qs_cost_diagonal_noalloc(int n, const int32_t *w_tenths, int32_t *diag_dev, int64_t *w_total_tenths,
+                                   int32_t *cmax_tenths, void *hip_stream)
+{
+    const char *where = "qs_cost_diagonal_noalloc";
+    if (n < 1 || n > QS_MAX_QUBITS_C64)
+        return fail(QS_ERR_ARG, "%s: n = %d outside 1..%d (the scratch array's limit)", where, n, QS_MAX_QUBITS_C64);
+    if (!diag_dev) return fail(QS_ERR_ARG, "%s: null diagonal buffer", where);
+    if (!aligned(diag_dev, 16)) return fail(QS_ERR_ARG, "%s: diagonal buffer must be 16-byte aligned", where);
+    int32_t wm[QS_MAX_QUBITS_C64 * QS_MAX_QUBITS_C64];  // host, on the stack
+    int64_t W = 0;
+    if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
+    const DiagScratch L = diag_scratch_layout(n, 1);
+    if (L.total > kNoallocDiag.total) return fail(QS_ERR_ARG, "%s: scratch of n = %d exceeds the array", where, n);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    char *scratch_dev = nullptr;
+    if (qs_status st = noalloc_scratch(&scratch_dev, where)) return st;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int32_t cmax = 0;
+    hipError_t he = build_diagonal(n, wm, diag_dev, scratch_dev, L, 0, st);
+    if (he == hipSuccess) he = hipMemcpyAsync(&cmax, scratch_dev + L.off_res, 4, hipMemcpyDeviceToHost, st);
+    // always wait: the queued copies read wm and write cmax in this frame
+    const hipError_t hs = hipStreamSynchronize(st);
+    if (he == hipSuccess) he = hs;
+    if (he != hipSuccess) return hip_fail(he, where);
+    if (w_total_tenths) *w_total_tenths = W;
+    if (cmax_tenths) *cmax_tenths = cmax;
+    return QS_OK;
 }
 
 qs_status qs_apply_cost_layer(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, double theta_zz)
@@ -1226,7 +1289,8 @@ qs_status qs_batch_create(int count, const qs_circuit *circuits, int prec, void 
                 return fail(QS_ERR_ARG, "circuit %d: n = %d outside %d..%d", i, c.n, T + 1, QS_BATCH_MAX_QUBITS);
             if (c.p < 1) return fail(QS_ERR_ARG, "circuit %d: p must be >= 1", i);
             int64_t W = 0;
-            if (qs_status st = weight_matrix(c.n, c.w_tenths, wms[i], &W)) return st;
+            if (c.n > 0) wms[i].resize((size_t)c.n * c.n);
+            if (qs_status st = weight_matrix(c.n, c.w_tenths, wms[i].data(), &W)) return st;
             nmax = std::max(nmax, c.n);
         }
         qs_batch b = new qs_batch_s();
@@ -1242,7 +1306,7 @@ qs_status qs_batch_create(int count, const qs_circuit *circuits, int prec, void 
         char *scratch = nullptr;
         he = hipMalloc(&scratch, L.total);
         for (int i = 0; i < count && he == hipSuccess; ++i)
-            he = build_diagonal(b->n[i], wms[i], (int32_t *)((char *)b->mem + b->off_diag[i]), scratch, L, i,
+            he = build_diagonal(b->n[i], wms[i].data(), (int32_t *)((char *)b->mem + b->off_diag[i]), scratch, L, i,
                                 b->stream);
         b->cmax.assign(count, 0);
         if (he == hipSuccess)
@@ -1362,9 +1426,9 @@ qs_status qs_noise_create(int n, int prec, const int32_t *w_tenths, void *hip_st
         *out = nullptr;
         if (n < 2 || n > kNoiseMaxQubits) return fail(QS_ERR_ARG, "n = %d outside 2..%d", n, kNoiseMaxQubits);
         if (prec != QS_C64 && prec != QS_C128) return fail(QS_ERR_ARG, "bad precision %d", prec);
-        std::vector<int32_t> wm;
+        std::vector<int32_t> wm((size_t)n * n);
         int64_t W = 0;
-        if (qs_status st = weight_matrix(n, w_tenths, wm, &W)) return st;
+        if (qs_status st = weight_matrix(n, w_tenths, wm.data(), &W)) return st;
         const char *where = "qs_noise_create";
         std::unique_ptr<qs_noise_s> h(new qs_noise_s);
         h->n = n;

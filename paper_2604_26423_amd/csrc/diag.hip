@@ -17,7 +17,7 @@ namespace qs {
 
 namespace {
 
-constexpr int kLowBits = 13;
+constexpr int kLowBits = kDiagLowBits;
 constexpr int kDiagThreads = 256;
 
 // Cut value restricted to vertices [0, L), by the double loop.  When L == n

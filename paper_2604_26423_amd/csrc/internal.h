@@ -276,6 +276,10 @@ hipError_t launch_cost_diagonal(int n, const int32_t *wmat_dev, int32_t *diag, i
                                 hipStream_t st, int sym = 0);
 int64_t diag_wg_count(int n, int sym = 0);
 
+// Vertices 0..12 (the low index bits) form the diagonal builder's shared
+// table; each workgroup of its main kernel owns one value of the other bits.
+constexpr int kDiagLowBits = 13;
+
 // Scratch for building diagonals of up to nmax qubits with nwg workgroups of
 // the main kernel: the weight matrix (nmax x nmax int32), the low-bit table
 // (2^13 int32), per-workgroup maxima, their partial maxima and `nres` int32

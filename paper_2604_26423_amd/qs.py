@@ -42,7 +42,7 @@ EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free
            "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
            "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free",
-           "qs_bandwidth_probe"]
+           "qs_bandwidth_probe", "qs_cost_diagonal_noalloc"]
 QS_BATCH_MAX_QUBITS = 30
 QS_NOISE_MAX_QUBITS = 12
 QS_NOISE_MAX_LAYERS = 4096
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         "qs_set_stream": ([vp, vp], i32),
         "qs_init_plus": ([vp], i32),
         "qs_cost_diagonal": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
+        "qs_cost_diagonal_noalloc": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
         "qs_cost_diagonal_sym": ([i32, vp, vp, _c_i64_p, _c_i32_p, vp], i32),
         "qs_apply_cost_layer": ([vp, vp, i64, dbl], i32),
         "qs_apply_mixer": ([vp, dbl], i32),
@@ -205,6 +206,16 @@ def qs_cost_diagonal(n: int, w_tenths, diag_dev, stream=None) -> tuple:
     W, cm = ctypes.c_int64(), ctypes.c_int32()
     _check(lib().qs_cost_diagonal(n, w.ctypes.data if w.size else None, _ptr(diag_dev), ctypes.byref(W),
                                   ctypes.byref(cm), _stream(stream)))
+    return int(W.value), int(cm.value)
+
+
+def qs_cost_diagonal_noalloc(n: int, w_tenths, diag_dev, stream=None) -> tuple:
+    """qs_cost_diagonal with its scratch in the library's static device array
+    (no device allocation); returns (W_t, C_max in tenths)."""
+    w = np.ascontiguousarray(np.asarray(w_tenths, dtype=np.int32))
+    W, cm = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().qs_cost_diagonal_noalloc(n, w.ctypes.data if w.size else None, _ptr(diag_dev), ctypes.byref(W),
+                                          ctypes.byref(cm), _stream(stream)))
     return int(W.value), int(cm.value)
 
 

@@ -129,6 +129,15 @@ def test_cost_diagonal_validation():
     w = np.ones(45, dtype=np.int32)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 0, w, FAKE, 0)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 35, w, FAKE, 0)
+    # the allocation-free variant rejects sizes beyond its static scratch, and
+    # bad arguments, before any device work
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_noalloc, 0, w, FAKE, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_noalloc, 35, np.ones(595, dtype=np.int32), FAKE, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_noalloc, 10, w, None, 0)
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_noalloc, 10, w, FAKE + 4, 0)
+    bad = w.copy()
+    bad[3] = -1
+    expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal_noalloc, 10, bad, FAKE, 0)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, w, None, 0)
     expect_status(qs.QS_ERR_ARG, qs.qs_cost_diagonal, 10, w, FAKE + 4, 0)
     bad = w.copy()

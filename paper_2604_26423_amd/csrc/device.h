@@ -199,6 +199,18 @@ __device__ __forceinline__ void rxt_reg_all(V (&v)[NR], uint32_t mask, R u)
     if constexpr (NR > 32) rxt_reg_bit<5>(v, sel_u<5>(mask, u));
 }
 
+// Tangent-form updates on the register bits of a compile-time mask M only.
+template <uint32_t M, typename V, int NR, typename R>
+__device__ __forceinline__ void rxt_reg_const(V (&v)[NR], R u)
+{
+    if constexpr (NR > 1 && (M & 1u)) rxt_reg_bit<0>(v, u);
+    if constexpr (NR > 2 && (M & 2u)) rxt_reg_bit<1>(v, u);
+    if constexpr (NR > 4 && (M & 4u)) rxt_reg_bit<2>(v, u);
+    if constexpr (NR > 8 && (M & 8u)) rxt_reg_bit<3>(v, u);
+    if constexpr (NR > 16 && (M & 16u)) rxt_reg_bit<4>(v, u);
+    if constexpr (NR > 32 && (M & 32u)) rxt_reg_bit<5>(v, u);
+}
+
 // Two-bit factors on register bits (K, K+1), K = 0..RB-2, selected by pmask.
 template <typename V, int NR, typename R>
 __device__ __forceinline__ void rxt_reg_pairs_all(V (&v)[NR], uint32_t pmask, R u)
@@ -292,6 +304,20 @@ __device__ __forceinline__ double imx_reg_all(const V (&l)[NR], const V (&p)[NR]
     if constexpr (NR > 8) g += sel_w<3>(mask) * imx_reg_bit<3>(l, p);
     if constexpr (NR > 16) g += sel_w<4>(mask) * imx_reg_bit<4>(l, p);
     if constexpr (NR > 32) g += sel_w<5>(mask) * imx_reg_bit<5>(l, p);
+    return g;
+}
+
+// The same sums over the register bits of a compile-time mask M.
+template <uint32_t M, typename V, int NR>
+__device__ __forceinline__ double imx_reg_const(const V (&l)[NR], const V (&p)[NR])
+{
+    double g = 0.0;
+    if constexpr (NR > 1 && (M & 1u)) g += imx_reg_bit<0>(l, p);
+    if constexpr (NR > 2 && (M & 2u)) g += imx_reg_bit<1>(l, p);
+    if constexpr (NR > 4 && (M & 4u)) g += imx_reg_bit<2>(l, p);
+    if constexpr (NR > 8 && (M & 8u)) g += imx_reg_bit<3>(l, p);
+    if constexpr (NR > 16 && (M & 16u)) g += imx_reg_bit<4>(l, p);
+    if constexpr (NR > 32 && (M & 32u)) g += imx_reg_bit<5>(l, p);
     return g;
 }
 

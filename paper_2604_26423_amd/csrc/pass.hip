@@ -7,13 +7,14 @@
 // kernels in tangent form do the same, two workgroups per CU; the others run
 // one persistent workgroup per CU that loads the next tile's vectors into
 // registers while it works on the current tile (see adjoint_variant).
+#include "plan.h"
 #include "tiles.h"
 
 namespace qs {
 
 namespace {
 
-template <typename V, int T, int TB, int MODE, int SH>
+template <typename V, int T, int TB, int MODE, int SH, int K = 0>
 __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
 {
     constexpr int NT = 1 << TB;
@@ -27,7 +28,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     }
     double acc[2] = {0.0, 0.0};
     for (int64_t tile = xcd_tile(pp.xcd_remap); tile < pp.ntiles; tile += gridDim.x)
-        fwd_tile<V, T, TB, MODE, SH>(pp, tile, lds, tab, acc, tid);
+        fwd_tile<V, T, TB, MODE, SH, K>(pp, tile, lds, tab, acc, tid);
     if (pp.readout) {
         block_sum(acc, red, tid, NT);
         if (tid == 0) {
@@ -42,7 +43,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
 // buffer.  ONE = true: one tile per workgroup, no prefetch, one-tile LDS
 // buffer, at most 128 registers (launch bounds), so that two workgroups share
 // a CU and overlap each other's memory and compute phases.
-template <typename V, int T, int TB, bool turnaround, int MODE, int SH, bool ONE>
+template <typename V, int T, int TB, bool turnaround, int MODE, int SH, bool ONE, int K = 0>
 __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg pp)
 {
     using Cfg = TileCfg<V, T, TB>;
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
             } else {
                 turn_load<V, T, TB>(pp, tile, p, tid);
             }
-            turn_compute<V, T, TB, MODE, PAIR>(pp, tile, p, dg, lds, acc, tid);
+            turn_compute<V, T, TB, MODE, PAIR, K>(pp, tile, p, dg, lds, acc, tid);
             if constexpr (PREFETCH) {
 #pragma unroll
                 for (int r = 0; r < NR; ++r) p[r] = np[r];
@@ -102,7 +103,7 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
             } else {
                 rev_load_vectors<V, T, TB>(pp, tile, p, l, tid);
             }
-            rev_tile<V, T, TB, MODE, SH, PAIR, LATE>(pp, tile, p, l, dg, lds, tab, acc, tid);
+            rev_tile<V, T, TB, MODE, SH, PAIR, LATE, K>(pp, tile, p, l, dg, lds, tab, acc, tid);
             if constexpr (PREFETCH) {
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
@@ -159,17 +160,56 @@ int tile_mode(const PassProg &pp, int T, int tb)
     return kModeTanSym;
 }
 
+// Compile-time stage tail K of a fixed-shape tangent-form kernel (see
+// stage_tail in plan.h and run_stage / unrun_stage in tiles.h), or 0 when the
+// pass's windows do not have the pattern the kernel assumes.  kind: 0 =
+// forward pass, 1 = turnaround, 2 = reverse pass.  The first stage a kernel
+// visits must end in its lowest K bits, the second (if any) in its highest K.
+int tail_k(const PassProg &pp, int T, int tb, int kind)
+{
+    if (pp.pairs) return 0;
+    const int rb = T - tb;
+    if (kind == 0) {
+        if (pp.has_pre)
+            return kernel_tail(stage_tail(pp.A, pp.targets, rb, false), stage_tail(pp.B, pp.targets, rb, false), true,
+                               rb);
+        return kernel_tail(stage_tail(pp.B, pp.targets, rb, false), 0, false, rb);
+    }
+    if (kind == 1)
+        return kernel_tail(stage_tail(pp.B, pp.targets, rb, false), stage_tail(pp.B, pp.targets, rb, true), true, rb);
+    if (pp.has_pre)
+        return kernel_tail(stage_tail(pp.B, pp.targets, rb, true), stage_tail(pp.A, pp.targets, rb, true), true, rb);
+    // a lone reverse stage ends in its highest K bits
+    const int t = stage_tail(pp.B, pp.targets, rb, true);
+    return t == rb ? rb : (t < 0 ? -t : 0);
+}
+
 namespace {
-template <int MODE, int SH>
+template <int MODE, int SH, int K = 0>
 void launch_pass_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     constexpr int FT = kFwdThreadBits;
     if (prec == 0)
-        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT, MODE, SH>), dim3((unsigned)grid), dim3(1 << FT), 0,
-                           st, pp);
+        hipLaunchKernelGGL((pass_kernel<float2, kTileBitsC64, FT, MODE, SH, K>), dim3((unsigned)grid), dim3(1 << FT),
+                           0, st, pp);
     else
         hipLaunchKernelGGL((pass_kernel<double2, kTileBitsC128, FT, MODE, SH>), dim3((unsigned)grid), dim3(1 << FT),
                            0, st, pp);
+}
+
+// complex64 tangent-form fixed shapes: the instantiation for the pass's tail
+template <int SH>
+void launch_pass_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+{
+    const int k = prec == 0 ? tail_k(pp, kTileBitsC64, kFwdThreadBits, 0) : 0;
+    switch (k) {
+    case 1: launch_pass_s<kModeTan, SH, 1>(prec, pp, grid, st); break;
+    case 2: launch_pass_s<kModeTan, SH, 2>(prec, pp, grid, st); break;
+    case 3: launch_pass_s<kModeTan, SH, 3>(prec, pp, grid, st); break;
+    case 4: launch_pass_s<kModeTan, SH, 4>(prec, pp, grid, st); break;
+    case 5: launch_pass_s<kModeTan, SH, 5>(prec, pp, grid, st); break;
+    default: launch_pass_s<kModeTan, SH>(prec, pp, grid, st); break;
+    }
 }
 
 // Forward shapes with their own instantiation: the first pass (|+>, phase,
@@ -179,10 +219,20 @@ void launch_pass_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 template <int MODE>
 void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
+    constexpr int kFirst = kShInit | kShPhase | kShPost, kJunc = kShPre | kShPhase | kShPost,
+                  kLast = kShPost | kShReadout;
+    if constexpr (MODE == kModeTan) {
+        switch (pass_shape(pp)) {
+        case kFirst: launch_pass_k<kFirst>(prec, pp, grid, st); return;
+        case kJunc: launch_pass_k<kJunc>(prec, pp, grid, st); return;
+        case kLast: launch_pass_k<kLast>(prec, pp, grid, st); return;
+        default: launch_pass_s<MODE, -1>(prec, pp, grid, st); return;
+        }
+    }
     switch (pass_shape(pp)) {
-    case kShInit | kShPhase | kShPost: launch_pass_s<MODE, kShInit | kShPhase | kShPost>(prec, pp, grid, st); break;
-    case kShPre | kShPhase | kShPost: launch_pass_s<MODE, kShPre | kShPhase | kShPost>(prec, pp, grid, st); break;
-    case kShPost | kShReadout: launch_pass_s<MODE, kShPost | kShReadout>(prec, pp, grid, st); break;
+    case kFirst: launch_pass_s<MODE, kFirst>(prec, pp, grid, st); break;
+    case kJunc: launch_pass_s<MODE, kJunc>(prec, pp, grid, st); break;
+    case kLast: launch_pass_s<MODE, kLast>(prec, pp, grid, st); break;
     default: launch_pass_s<MODE, -1>(prec, pp, grid, st); break;
     }
 }
@@ -194,6 +244,23 @@ void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st
     const dim3 g((unsigned)grid), b(1 << AT);
     if (prec == 0) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
     else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
+}
+
+// complex64 one-tile tangent-form kernels: the instantiation for the pass's tail
+template <bool TURN, int SH>
+void launch_adjoint_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
+{
+    constexpr int AT = kAdjThreadBits;
+    const int k = prec == 0 ? tail_k(pp, kTileBitsC64, AT, TURN ? 1 : 2) : 0;
+    const dim3 g((unsigned)grid), b(1 << AT);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, pp); };
+    switch (k) {
+    case 1: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 1>); break;
+    case 2: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 2>); break;
+    case 3: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 3>); break;
+    case 4: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 4>); break;
+    default: launch_adjoint_s<kModeTan, TURN, SH, true>(prec, pp, grid, st); break;
+    }
 }
 
 // Adjoint kernel variants.  kAdjPersistent: the runtime-shape persistent
@@ -221,6 +288,18 @@ int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
 template <int MODE>
 void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
+    if constexpr (MODE == kModeTan) {
+        if (prec == 0) {
+            switch (adjoint_variant(prec, pp, turnaround, MODE)) {
+            case kAdjOneTurn: launch_adjoint_k<true, -1>(prec, pp, grid, st); return;
+            // (the reverse of a plain pass and the reverse junction keep runtime
+            // masks: with compile-time tails their code needs more than the 128
+            // registers of two workgroups per CU and spills)
+            case kAdjOneFirst: launch_adjoint_k<false, kShInit | kShPhase | kShPost>(prec, pp, grid, st); return;
+            default: break;
+            }
+        }
+    }
     switch (adjoint_variant(prec, pp, turnaround, MODE)) {
     case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true>(prec, pp, grid, st); break;
     case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true>(prec, pp, grid, st); break;

@@ -90,6 +90,49 @@ inline WinSeq plan_windows(int start, uint32_t targets, int T, int tb)
     return plan_windows(start, targets, 0u, T, tb);
 }
 
+// Tail of a stage: the stage's windows visited forward or in reverse, each
+// applying the single factors in it that no earlier-visited window applied.
+// Returns +k when every window but the last visited applies all rb of its
+// register bits and the last applies its lowest k; -k when the last applies
+// its highest k; 0 for any other pattern.  (k = rb: the last window is full
+// too, and +rb is returned.)  The planner's stages always have such a tail,
+// which lets a kernel fix at compile time which register bits a window
+// updates instead of updating idle bits with a zero angle.
+inline int stage_tail(const WinSeq &w, uint32_t targets, int rb, bool reverse)
+{
+    if (w.cnt < 1 || w.cnt > kMaxWindows) return 0;
+    const uint32_t full = (1u << rb) - 1u;
+    uint32_t done = 0;
+    for (int j = 0; j < w.cnt; ++j) {
+        const int i = reverse ? w.cnt - 1 - j : j;
+        const uint32_t m = (targets >> w.s[i]) & full & ~(done >> w.s[i]);
+        done |= m << w.s[i];
+        if (j < w.cnt - 1) {
+            if (m != full) return 0;
+            continue;
+        }
+        const int k = __builtin_popcount(m);
+        if (k == 0) return 0;
+        if (m == (1u << k) - 1u) return k;
+        if (m == (((1u << k) - 1u) << (rb - k))) return -k;
+        return 0;
+    }
+    return 0;
+}
+
+// Compile-time tail of a kernel that visits one or two stages of a pass:
+// the first stage must end in the low k bits (+k) and the second, if any, in
+// the high k bits (-k), with the same k (a full last window, k = rb, fits
+// either).  Returns k, or 0 when the pass does not have this shape.
+inline int kernel_tail(int first, int second, bool two_stages, int rb)
+{
+    if (first <= 0) return 0;
+    if (!two_stages) return first;
+    const int k = first;
+    if (second == -k || (k == rb && second == rb)) return k;
+    return 0;
+}
+
 // Complement-symmetric storage.  Every state of the circuit satisfies
 // psi(x) = psi(~x) (the cost function is invariant under complementing all
 // bits, and so are |+>^n and the mixer), so only the half with bit n-1 = 0

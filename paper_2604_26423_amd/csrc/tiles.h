@@ -214,14 +214,51 @@ __device__ __forceinline__ double imx_window(const V (&l)[NR], const V (&p)[NR],
     }
 }
 
+// Register bits that the last visited window of a stage updates when the
+// kernel fixes the stage's tail at compile time (stage_tail in plan.h):
+// TAIL = +k the lowest k, TAIL = -k the highest k.
+template <int RB, int TAIL>
+constexpr uint32_t tail_mask()
+{
+    constexpr int k = TAIL > 0 ? TAIL : -TAIL;
+    return TAIL > 0 ? (1u << k) - 1u : ((1u << k) - 1u) << (RB - k);
+}
+
 // Forward butterfly stage: walk the windows of `seq`, applying each factor
 // once, in the first window that holds it.  The first window of every stage
 // is the current layout and consecutive windows differ (checked on the host),
 // so the branch-free modes exchange unconditionally from the second window on.
-template <int RB, int MODE, typename V, int NR>
+// TAIL != 0 (tangent form, single factors only): every window but the last
+// applies all its register bits and the last those of tail_mask, fixed at
+// compile time, so no idle bit is updated with a zero angle.
+template <int RB, int MODE, int TAIL = 0, typename V, int NR>
 __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq, uint32_t targets, uint32_t pairs,
                                           const RxStage &st, int &cur, int tid)
 {
+    if constexpr (TAIL != 0) {
+        static_assert(MODE == kModeTan, "compile-time tails are for single-factor tangent-form stages");
+        using R = typename Real<V>::T;
+        const R u = (R)st.u;
+        const int last = seq.cnt - 1;
+        // window indices go through opaque(): the peeled last window's layout
+        // is loop-invariant across tiles, and hoisted its per-register LDS
+        // offsets would occupy scalar registers for the whole kernel
+        for (int i = 0; i < last; ++i) {
+            if (i > 0) {
+                const int w = opaque(seq.s[i]);
+                exchange<RB>(v, lds, cur, w, tid);
+                cur = w;
+            }
+            rxt_reg_const<(1u << RB) - 1u>(v, u);
+        }
+        if (last > 0) {
+            const int w = opaque(seq.s[last]);
+            exchange<RB>(v, lds, cur, w, tid);
+            cur = w;
+        }
+        rxt_reg_const<tail_mask<RB, TAIL>()>(v, u);
+        return;
+    }
     uint32_t done = 0, pdone = 0;
     for (int i = 0; i < seq.cnt; ++i) {
         const int w = seq.s[i];
@@ -246,14 +283,42 @@ __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq,
 // factor accumulate Im <lam| X.. |psi> (invariant under the stage applied to
 // both), then apply RX(-theta) to both.  In tangent form both vectors carry
 // 1/cos^j after j factors, so the terms are rescaled by cos^(2j).
-template <int RB, int MODE, bool PAIR, typename V, int NR>
+template <int RB, int MODE, bool PAIR, int TAIL = 0, typename V, int NR>
 __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
                                             uint32_t targets, uint32_t pairs, const RxStage &st, int &cur, int tid,
                                             double &gx)
 {
-    uint32_t done = 0, pdone = 0;
     double sc = 1.0;
     const double c2 = st.tan ? st.c * st.c : 1.0;
+    if constexpr (TAIL != 0) {
+        // windows in reverse order; all but the last visited (index 0) full
+        static_assert(MODE == kModeTan, "compile-time tails are for single-factor tangent-form stages");
+        using R = typename Real<V>::T;
+        constexpr uint32_t FULL = (1u << RB) - 1u, LAST = tail_mask<RB, TAIL>();
+        const R u = (R)(-st.u);
+        auto to = [&](int w) {
+            if constexpr (PAIR) {
+                exchange2<RB>(p, l, lds, cur, w, tid);
+            } else {
+                exchange<RB>(p, lds, cur, w, tid);
+                exchange<RB>(l, lds, cur, w, tid);
+            }
+            cur = w;
+        };
+        for (int i = seq.cnt - 1; i > 0; --i) {
+            if (i < seq.cnt - 1) to(opaque(seq.s[i]));
+            gx += sc * imx_reg_const<FULL>(l, p);
+            rxt_reg_const<FULL>(p, u);
+            rxt_reg_const<FULL>(l, u);
+            for (int b = 0; b < RB; ++b) sc *= c2;
+        }
+        if (seq.cnt > 1) to(opaque(seq.s[0]));  // (opaque: see run_stage)
+        gx += sc * imx_reg_const<LAST>(l, p);
+        rxt_reg_const<LAST>(p, u);
+        rxt_reg_const<LAST>(l, u);
+        return;
+    }
+    uint32_t done = 0, pdone = 0;
     for (int i = seq.cnt - 1; i >= 0; --i) {
         const int w = seq.s[i];
         if (MODE == kModeGeneral ? w != cur : i < seq.cnt - 1) {
@@ -290,7 +355,9 @@ __device__ __forceinline__ void load_phase_table(V *tab, const V *src, int level
 }
 
 // Forward pass on one tile; with pp.readout, acc += (sum |a|^2, sum |a|^2 C_t).
-template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1>
+// K > 0 (a fixed shape SH in tangent form): the stages' tails are fixed at
+// compile time, +K for the first stage and -K for the second (run_stage).
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, int K = 0>
 __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *lds, const V *tab, double (&acc)[2],
                                          int tid)
 {
@@ -322,14 +389,16 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     } else {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
     }
-    if (has_pre) run_stage<RB, MODE>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
+    static_assert(K == 0 || (SH >= 0 && MODE == kModeTan), "compile-time tails need a fixed tangent-form shape");
+    constexpr int TAIL_B = K == 0 ? 0 : ((SH & kShPre) != 0 ? -K : K);  // B is the second stage after A
+    if (has_pre) run_stage<RB, MODE, K>(v, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid);
     if (has_phase) {
         V f[NR];
         phase_factors(tab, pp.phase_levels, dg, f);
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = cmul(v[r], f[r]);
     }
-    if (has_post) run_stage<RB, MODE>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
+    if (has_post) run_stage<RB, MODE, TAIL_B>(v, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     // tangent-form factor of a pass without a phase table (scaling by 1 when
     // it is 1 costs less than a branch in a fixed-shape kernel)
     if (!has_phase && (KS || pp.factor != 1.0)) {
@@ -386,7 +455,7 @@ __device__ __forceinline__ void turn_load_diag(const PassProg &pp, int64_t tile,
                           [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
 }
 
-template <typename V, int T, int TB, int MODE = kModeGeneral, bool PAIR = true>
+template <typename V, int T, int TB, int MODE = kModeGeneral, bool PAIR = true, int K = 0>
 __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                              const int32_t (&dg)[TileCfg<V, T, TB>::NR], V *lds,
                                              double (&acc)[kSlots], int tid)
@@ -400,7 +469,8 @@ __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
     V l[NR];
     int cur = opaque(pp.load_win);
-    run_stage<RB, MODE>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
+    // K > 0: the stage forward ends in +K, its reverse in -K (fixed at compile time)
+    run_stage<RB, MODE, K>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
     // cur is now the final layout, the one the diagonal was loaded in
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -411,12 +481,12 @@ __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V
         acc[2] += pr * (double)C;
         l[r] = scale_v(p[r], (R)(((double)C - pp.lam_shift) * 0.1));
     }
-    unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+    unrun_stage<RB, MODE, PAIR, -K>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
     for_each_reg<NR>(win_addr(tid, cur, RB, base, gg.c, gg.q0),
                      [&](int r, int64_t g) { lam[g] = scale_v(l[r], fpost); });
 }
 
-template <typename V, int T, int TB, int MODE = kModeGeneral>
+template <typename V, int T, int TB, int MODE = kModeGeneral, int K = 0>
 __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *lds, double (&acc)[kSlots], int tid)
 {
     constexpr int NR = TileCfg<V, T, TB>::NR;
@@ -424,7 +494,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
     int32_t dg[NR];
     turn_load_diag<V, T, TB>(pp, tile, dg, tid);
     turn_load<V, T, TB>(pp, tile, p, tid);
-    turn_compute<V, T, TB, MODE>(pp, tile, p, dg, lds, acc, tid);
+    turn_compute<V, T, TB, MODE, true, K>(pp, tile, p, dg, lds, acc, tid);
 }
 
 // Reverse pass, loads: psi and lambda of a tile in the pass's load layout, and
@@ -460,7 +530,8 @@ __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, 
 // first forward pass (init) only accumulates and writes nothing; with
 // pp.psi_out null only lambda is stored (checkpointed psi).  LATE: dg is
 // loaded here at the phase point rather than by the caller.
-template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true, bool LATE = false>
+template <typename V, int T, int TB, int MODE = kModeGeneral, int SH = -1, bool PAIR = true, bool LATE = false,
+          int K = 0>
 __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                          V (&l)[TileCfg<V, T, TB>::NR], int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                          V *lds, const V *tab, double (&acc)[kSlots], int tid)
@@ -486,8 +557,12 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     // gradient sums taken on the vectors without fpost (phase point) or with
     // an extra fpre (pre stage) are corrected by fpost^2 and 1 / fpre^2.
     const bool fold = TAN && has_phase && !init;
+    // K > 0 (a fixed tangent-form shape): the post stage, undone first, ends
+    // in +K when the pre stage follows it and in -K when it is the only stage
+    static_assert(K == 0 || (SH >= 0 && MODE == kModeTan), "compile-time tails need a fixed tangent-form shape");
+    constexpr int TAIL_B = K == 0 ? 0 : ((SH & kShPre) != 0 ? K : -K);
     if (has_post) {
-        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
+        unrun_stage<RB, MODE, PAIR, TAIL_B>(p, l, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid, acc[0]);
         if ((TAN || pp.post.tan) && !fold) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -517,7 +592,7 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
     }
     if (has_pre) {
         double gpre = 0.0;
-        unrun_stage<RB, MODE, PAIR>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, gpre);
+        unrun_stage<RB, MODE, PAIR, -K>(p, l, lds, pp.A, pp.targets, pp.pairs, pp.pre, cur, tid, gpre);
         acc[2] += fold ? gpre / (pp.fpre * pp.fpre) : gpre;
         if ((TAN || pp.pre.tan) && !fold) {
 #pragma unroll

@@ -1,7 +1,8 @@
 // Host-only driver for the pass planner (plan.h) under AddressSanitizer and
 // UndefinedBehaviorSanitizer: every n, both precisions, both layouts, the
 // window sequences for every kernel width.  Checks that each stage's windows
-// stay inside the tile and cover its factors.  Built and run by
+// stay inside the tile and cover its factors, computes every stage's tail in
+// both directions, and drives the planner past its window limit.  Built and run by
 // tests/test_sanitizers.py; prints "ok <windows>" and exits 0.
 #include <cstdio>
 
@@ -9,7 +10,7 @@
 
 int main()
 {
-    long windows = 0;
+    long windows = 0, tails = 0;
     for (int prec = 0; prec < 2; ++prec) {
         const int T = qs::tile_bits(prec);
         for (int sym = 0; sym < 2; ++sym) {
@@ -45,11 +46,28 @@ int main()
                             }
                             windows += w->cnt;
                         }
+                        // stage tails (compile-time masks of the last window), both directions
+                        for (const qs::WinSeq *w : {&A, &B})
+                            for (bool rev : {false, true}) {
+                                const int t = qs::stage_tail(*w, g.pairs ? 0u : g.targets, rb, rev);
+                                if (t < -rb || t > rb) {
+                                    std::printf("tail %d outside +-%d (n=%d)\n", t, rb, n);
+                                    return 1;
+                                }
+                                tails += t != 0;
+                            }
                     }
                 }
             }
         }
     }
-    std::printf("ok %ld\n", windows);
+    // a stage that needs more windows than a sequence holds (one-bit windows
+    // over 13 targets): the planner flags it, and nothing reads past the array
+    const qs::WinSeq over = qs::plan_windows(12, (1u << 13) - 1u, 13, 12);
+    if (over.cnt != qs::kMaxWindows + 1 || qs::stage_tail(over, (1u << 13) - 1u, 1, false) != 0) {
+        std::printf("overflow not flagged (cnt %d)\n", over.cnt);
+        return 1;
+    }
+    std::printf("ok %ld %ld\n", windows, tails);
     return 0;
 }

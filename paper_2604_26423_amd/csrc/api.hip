@@ -119,7 +119,7 @@ struct qs_state_s {
     void *psi = nullptr;
     bool own = false;
     hipStream_t stream = nullptr;
-    DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer;
+    DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer, tab;
     bool prof = false;
     std::vector<ProfRec> recs;
 };
@@ -278,6 +278,7 @@ qs_status launch_tiles(qs_state s, PassProg &pp, int adjoint, int turnaround, in
     // adjoint: 0 = forward pass, 1 = turnaround, 2 = reverse pass
     const int64_t grid = tile_grid(s->prec, adjoint, pp);
     pp.xcd_remap = (grid % 8 == 0) ? 1 : 0;
+    pp.tab = s->tab.p;
     Launch L(s, kind, bytes);
     HIPCHK(adjoint ? launch_adjoint_pass(s->prec, pp, turnaround, grid, s->stream)
                    : launch_pass(s->prec, pp, grid, s->stream),
@@ -301,7 +302,8 @@ hipError_t ensure_partials(qs_state s, int64_t count)
     hipError_t e = s->partials.ensure((size_t)count * kSlots * sizeof(double));
     if (e != hipSuccess) return e;
     e = s->tmp.ensure((size_t)std::max<int64_t>(reduce_tmp_doubles(count), kSlots) * sizeof(double));
-    return e;
+    if (e != hipSuccess) return e;
+    return s->tab.ensure(pass_table_bytes());
 }
 
 // Small zero-fill kernel (kept out of hipMemsetAsync so that the work can be

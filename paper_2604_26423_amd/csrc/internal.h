@@ -48,6 +48,8 @@ struct PassProg {
                           // buffer (checkpointing forward), or null (reverse
                           // pass reading a checkpoint: psi is not stored)
     const int32_t *diag;  // cost diagonal in tenths
+    void *tab;            // phase table of the pass's cost layer (kTabMax entries of float2 / double2),
+                          // written by the launcher's table kernel just before the pass
     double *partials;     // kSlots doubles per workgroup
     int64_t ntiles;       // 2^(n - T); workgroups loop over tiles
     int n, c, q0;
@@ -152,6 +154,8 @@ __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_
 
 // Host-side launchers (one per kernel family); all return hipError_t.
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
+// Bytes of the device buffer PassProg::tab points to (any precision).
+size_t pass_table_bytes();
 int phase_table_levels(int64_t W);
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid,
                                hipStream_t st);

@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
     __shared__ double red[kSlots * (NT / 64)];
     const int tid = threadIdx.x;
     if (pp.has_phase) {
-        build_phase_table(tab, pp.phase_levels, pp.theta_zz, pp.W, pp.factor, tid, NT);
+        load_phase_table(tab, static_cast<const V *>(pp.tab), pp.phase_levels, tid, NT);
         __syncthreads();
     }
     double acc[2] = {0.0, 0.0};
@@ -36,6 +36,15 @@ __global__ void __launch_bounds__(1 << TB) pass_kernel(PassProg pp)
             pp.partials[blockIdx.x * kSlots + 1] = acc[1];
         }
     }
+}
+
+// The phase table of a pass (see build_phase_table): the same for every
+// workgroup, so it is evaluated once, by one workgroup, into pp.tab, and each
+// workgroup of the pass copies it into LDS.
+template <typename V>
+__global__ void __launch_bounds__(256) phase_table_kernel(V *tab, int levels, double theta, int64_t W, double f)
+{
+    build_phase_table(tab, levels, theta, W, f, threadIdx.x, 256);
 }
 
 // ONE = false: persistent (one workgroup per CU), prefetching the next
@@ -56,10 +65,7 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
     __shared__ double red[kSlots * (NT / 64)];
     const int tid = threadIdx.x;
     if (pp.has_phase) {
-        // reverse passes in tangent form fold the stages' factors into the
-        // table (see rev_tile)
-        const bool fold = !turnaround && MODE != kModeGeneral && !pp.init;
-        build_phase_table(tab, pp.phase_levels, pp.theta_zz, pp.W, fold ? pp.factor : 1.0, tid, NT);
+        load_phase_table(tab, static_cast<const V *>(pp.tab), pp.phase_levels, tid, NT);
         __syncthreads();
     }
     double acc[kSlots] = {0.0, 0.0, 0.0, 0.0};
@@ -123,6 +129,8 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
 }  // namespace
 
 int phase_table_levels(int64_t W) { return phase_levels(W); }
+
+size_t pass_table_bytes() { return (size_t)kTabMax * sizeof(double2); }
 
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
 {
@@ -322,8 +330,26 @@ int64_t tile_grid(int prec, int adjoint, const PassProg &pp)
                                                                             : pp.ntiles;
 }
 
+namespace {
+// Evaluate the table of a phase pass into pp.tab, ahead of the pass on the
+// same stream.  f: the real factor folded into the table.
+hipError_t launch_phase_table(int prec, const PassProg &pp, double f, hipStream_t st)
+{
+    if (!pp.has_phase) return hipSuccess;
+    if (!pp.tab) return hipErrorInvalidValue;
+    if (prec == 0)
+        hipLaunchKernelGGL(phase_table_kernel<float2>, dim3(1), dim3(256), 0, st, static_cast<float2 *>(pp.tab),
+                           pp.phase_levels, pp.theta_zz, pp.W, f);
+    else
+        hipLaunchKernelGGL(phase_table_kernel<double2>, dim3(1), dim3(256), 0, st, static_cast<double2 *>(pp.tab),
+                           pp.phase_levels, pp.theta_zz, pp.W, f);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
+    if (hipError_t e = launch_phase_table(prec, pp, pp.factor, st)) return e;
     switch (tile_mode(pp, tile_bits(prec), kFwdThreadBits)) {
     case kModeTan: launch_pass_m<kModeTan>(prec, pp, grid, st); break;
     case kModeTanSym: launch_pass_m<kModeTanSym>(prec, pp, grid, st); break;
@@ -334,7 +360,12 @@ hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t s
 
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
-    switch (tile_mode(pp, tile_bits(prec), kAdjThreadBits)) {
+    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
+    // reverse passes in tangent form fold the stages' factors into the table
+    // (see rev_tile)
+    const bool fold = !turnaround && mode != kModeGeneral && !pp.init;
+    if (hipError_t e = launch_phase_table(prec, pp, fold ? pp.factor : 1.0, st)) return e;
+    switch (mode) {
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;
     default:

@@ -191,6 +191,15 @@ qs_status qs_apply_mixer(qs_state s, double theta_x);
  * qs_apply_mixer, computed with fewer passes over memory.
  * exp_c, norm (host, nullable): when exp_c is non-null the readout of
  * qs_expect is fused into the last pass and returned (synchronises).
+ * diag_dev is the cost diagonal of the graph (qs_cost_diagonal).  In the full
+ * layout, for states larger than one workgroup's tile, the passes evaluate
+ * C_t[x] in registers from the weights the diagonal encodes (C_t at the
+ * one- and two-hot indices: C(e_i) = deg_i, C(e_i + e_j) = deg_i + deg_j -
+ * 2 w_ij) instead of reading it: the same integers, without the diagonal's
+ * 4 bytes per amplitude.  The weights are checked against 1024 sampled
+ * entries, diag[0] = 0, their degrees and w_total_tenths; a diagonal that
+ * fails (not the cut function of nonnegative integer weights) is read entry
+ * by entry.  The same holds for qs_adjoint_grad and qs_adjoint_grad_store.
  */
 qs_status qs_forward(qs_state s, const int32_t *diag_dev, int64_t w_total_tenths, int p,
                      const double *theta_zz, const double *theta_x, double *exp_c, double *norm);

@@ -119,7 +119,7 @@ struct qs_state_s {
     void *psi = nullptr;
     bool own = false;
     hipStream_t stream = nullptr;
-    DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer, tab;
+    DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer, tab, wts, ctab;
     bool prof = false;
     std::vector<ProfRec> recs;
 };
@@ -259,9 +259,28 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     return pp;
 }
 
-PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb)
+// kind: 0 = forward pass, 1 = turnaround, 2 = reverse pass (the cut table is
+// attached when the kernel for the pass takes one).
+PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb, int kind = 0)
 {
-    return make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb, s->sym);
+    PassProg pp = make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb, s->sym);
+    if (!s->sym && s->ctab.p && s->wts.p && pass_takes_cut_table(s->prec, pp, kind)) {
+        pp.ctab = (int32_t *)s->ctab.p;
+        pp.wts = (const int32_t *)s->wts.p;
+    }
+    return pp;
+}
+
+// Tile passes of the full layout evaluate C_t in registers (see the cut-value
+// notes in internal.h): recover the weights from the diagonal of this call
+// and size the per-pass cut table.
+qs_status prepare_cut(qs_state s, const Circuit &cc, const char *where)
+{
+    if (s->sym || s->n <= tile_bits(s->prec)) return QS_OK;
+    HIPCHK(s->wts.ensure((size_t)kWtSize * sizeof(int32_t)), where);
+    HIPCHK(s->ctab.ensure((size_t)cut_table_entries(s->n, s->prec) * sizeof(int32_t)), where);
+    HIPCHK(launch_cut_weights(cc.diag, s->n, cc.W, (int32_t *)s->wts.p, s->stream), where);
+    return QS_OK;
 }
 
 // Pass plan of a state's layout.
@@ -293,7 +312,7 @@ double pass_bytes(qs_state s, const PassProg &pp)
 {
     const double dim = ldexp(1.0, s->n), a = (double)amp_bytes(s->prec);
     double b = dim * a * (pp.init ? 1.0 : 2.0);
-    if (pp.has_phase || pp.readout) b += dim * 4.0;
+    if ((pp.has_phase || pp.readout) && !pp.ctab) b += dim * 4.0;
     return b;
 }
 
@@ -420,6 +439,7 @@ qs_status run_forward(qs_state s, const Circuit &cc, bool readout, const char *w
     std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     if (readout) ks.back().readout = 1;
     HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
+    if (qs_status st = prepare_cut(s, cc, where)) return st;
     int64_t grid = 0;
     for (const KSpec &k : ks) {
         PassProg pp = make_prog(s, geo[k.pass], k, cc, kFwdThreadBits);
@@ -501,7 +521,9 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
     const int64_t ntiles = (int64_t)1 << (s->n - T);
     HIPCHK(ensure_partials(s, ntiles), where);  // no tile kernel has more workgroups than tiles
+    if (qs_status st = prepare_cut(s, cc, where)) return st;
     const double dim = ldexp(1.0, s->n), ab = (double)amp_bytes(s->prec);
+
     int64_t grid = 0;
 
     const int P = (int)ks.size();
@@ -522,9 +544,10 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     // turnaround: the last pass forward, lambda = C psi, the pass undone
     {
         const KSpec &k = ks.back();
-        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 1);
         pp.lam = lam;
-        if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_TURNAROUND, dim * (ab + 4 + ab), &grid, where))
+        if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_TURNAROUND, dim * (2.0 * ab + (pp.ctab ? 0.0 : 4.0)),
+                                        &grid, where))
             return st;
         const int map[kSlots] = {2 + cc.p + k.post, 0, 1, -1};
         if (qs_status st = run_reduce(s, grid, map, 1, where)) return st;
@@ -532,14 +555,14 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     // reverse passes
     for (int i = (int)ks.size() - 2; i >= 0; --i) {
         const KSpec &k = ks[i];
-        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits);
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 2);
         pp.lam = lam;
         pp.load_win = pp.final_win;
         if (ckpt) {
             pp.psi = ck(i);
             pp.psi_out = nullptr;
         }
-        const double by = dim * ab * (pp.init ? 2.0 : ckpt ? 3.0 : 4.0) + (pp.has_phase ? dim * 4.0 : 0.0);
+        const double by = dim * ab * (pp.init ? 2.0 : ckpt ? 3.0 : 4.0) + (pp.has_phase && !pp.ctab ? dim * 4.0 : 0.0);
         if (qs_status st = launch_tiles(s, pp, 2, 0, QS_KIND_ADJOINT, by, &grid, where)) return st;
         const int map[kSlots] = {k.post >= 0 ? 2 + cc.p + k.post : -1, k.phase >= 0 ? 2 + k.phase : -1,
                                  k.pre >= 0 ? 2 + cc.p + k.pre : -1, -1};

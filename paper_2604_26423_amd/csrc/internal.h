@@ -50,6 +50,10 @@ struct PassProg {
     const int32_t *diag;  // cost diagonal in tenths
     void *tab;            // phase table of the pass's cost layer (kTabMax entries of float2 / double2),
                           // written by the launcher's table kernel just before the pass
+    int32_t *ctab;        // cut table of the pass (layout kCt* below), written by the launcher just
+                          // before the pass, from which the pass evaluates C_t in registers instead of
+                          // loading the diagonal; null: the pass loads the diagonal
+    const int32_t *wts;   // weights recovered from the diagonal (layout kWt* below), when ctab is set
     double *partials;     // kSlots doubles per workgroup
     int64_t ntiles;       // 2^(n - T); workgroups loop over tiles
     int n, c, q0;
@@ -75,6 +79,35 @@ struct PassProg {
                           // the weights (C - c) of the phase gradients; any c gives the same
                           // gradients, c = W_t / 2 keeps the terms small (see tiles.h)
 };
+
+// ---- cut values in registers ----
+//
+// C_t(x) = sum_{i<j} w_ij [x_i != x_j] is a cut function, so for disjoint bit
+// sets A, B: C(A | B) = C(A) + C(B) - 2 w(A, B), w(A, B) = sum_{i in A, j in B}
+// w_ij.  At the point of a pass where it needs C_t, a register r of thread t
+// holds the amplitude x = A | B_t | D_r: A the tile's bits outside the tile
+// (from the workgroup index), B_t the thread's tile bits, D_r the register
+// bits of r.  With Db_i = sum_{j in A} w_ij and Dt_k = sum_{i in B_t} w_ik,
+//   C(x) = C(A) + C(B_t) + C(D_r) - 2 sum_{i in B_t} Db_i
+//          - 2 sum_{k in D_r} (Db_k + Dt_k).
+// The cut table of a pass holds C(D_r) for every r (uniform), C(B_t) and Dt_k
+// for every thread, and C(A) and Db_i for every tile (one 64-byte row, a
+// scalar load); the sums above are exact in uint32 (C_t < 2^31).
+//
+// The weights are recovered from the diagonal itself: C(e_i) = deg_i and
+// C(e_i | e_j) = deg_i + deg_j - 2 w_ij.  A sample of the diagonal is checked
+// against them; if the diagonal is not the cut function of nonnegative
+// integer weights summing to W_t, the table says so and the passes load the
+// diagonal instead.
+constexpr int kWtStride = 64;                     // row stride of the weight matrix
+constexpr int kWtDeg = kWtStride * kWtStride;     // deg_i, i < 64
+constexpr int kWtOk = kWtDeg + kWtStride;         // 1: weights reproduce the diagonal
+constexpr int kWtSize = kWtOk + 1;
+constexpr int kCtCreg = 0;                        // C(D_r), r < 2^RB (RB <= 5)
+constexpr int kCtValid = 32;                      // copy of the weights' ok flag
+constexpr int kCtThr = 64;                        // per thread: C(B_t), Dt_0 .. Dt_{RB-1}, 8 entries
+constexpr int kCtTile = kCtThr + 8 * 512;         // per tile: C(A), Db_0 .. Db_{T-1}, 16 entries
+constexpr int kCtSamples = 1024;                  // diagonal entries checked against the weights
 
 // ---- index maps of a tile pass (host and device) ----
 
@@ -156,6 +189,14 @@ __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
 // Bytes of the device buffer PassProg::tab points to (any precision).
 size_t pass_table_bytes();
+// Recover the weights of the cut function in diag (2^n entries, full layout)
+// into wts (kWtSize int32) and check them against the diagonal.
+hipError_t launch_cut_weights(const int32_t *diag, int n, int64_t W, int32_t *wts, hipStream_t st);
+// int32 entries of a cut table (PassProg::ctab) for 2^n amplitudes.
+int64_t cut_table_entries(int n, int prec);
+// Whether the kernel picked for pp (kind 0 = forward pass, 1 = turnaround,
+// 2 = reverse pass) takes C_t from a cut table; pp.ctab must be null otherwise.
+bool pass_takes_cut_table(int prec, const PassProg &pp, int kind);
 int phase_table_levels(int64_t W);
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid,
                                hipStream_t st);

@@ -47,6 +47,127 @@ __global__ void __launch_bounds__(256) phase_table_kernel(V *tab, int levels, do
     build_phase_table(tab, levels, theta, W, f, threadIdx.x, 256);
 }
 
+// Weights of the cut function that a full-layout diagonal encodes, and a
+// check that they reproduce it (see the cut-value notes in internal.h).  One
+// workgroup.  wts: kWtSize int32.
+__global__ void __launch_bounds__(256) cut_weights_kernel(const int32_t *__restrict__ diag, int n, int64_t W,
+                                                          int32_t *__restrict__ wts)
+{
+    __shared__ int32_t w[kWtStride * kWtStride];
+    __shared__ int32_t deg[kWtStride];
+    __shared__ int bad;
+    __shared__ unsigned long long twice_w;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        bad = diag[0] != 0;
+        twice_w = 0;
+    }
+    for (int i = tid; i < kWtStride; i += 256) deg[i] = i < n ? diag[swz((int64_t)1 << i)] : 0;
+    __syncthreads();
+    for (int idx = tid; idx < kWtStride * kWtStride; idx += 256) {
+        const int i = idx / kWtStride, j = idx % kWtStride;
+        int32_t v = 0;
+        if (i < n && j < n && i != j) {
+            const int64_t d = (int64_t)deg[i] + deg[j] - diag[swz(((int64_t)1 << i) | ((int64_t)1 << j))];
+            if (d < 0 || (d & 1)) atomicOr(&bad, 1);
+            v = (int32_t)(d >> 1);
+        }
+        w[idx] = v;
+    }
+    __syncthreads();
+    // deg_i = sum_j w_ij and W_t = sum_{i<j} w_ij
+    if (tid < n) {
+        int64_t rs = 0;
+        for (int j = 0; j < n; ++j) rs += w[tid * kWtStride + j];
+        if (rs != deg[tid]) atomicOr(&bad, 1);
+        atomicAdd(&twice_w, (unsigned long long)rs);
+    }
+    __syncthreads();
+    if (tid == 0 && twice_w != 2ull * (unsigned long long)W) bad = 1;
+    // sampled entries: C(x) = sum_{i in x} deg_i - 2 sum_{i<j in x} w_ij
+    for (int k = tid; k < kCtSamples; k += 256) {
+        const uint64_t x = n == 0 ? 0 : ((uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull) >> (64 - n);
+        int64_t cx = 0;
+        for (uint64_t a = x; a; a &= a - 1) {
+            const int i = __builtin_ctzll(a);
+            cx += deg[i];
+            for (uint64_t b = a & (a - 1); b; b &= b - 1) cx -= 2 * (int64_t)w[i * kWtStride + __builtin_ctzll(b)];
+        }
+        if (cx != (int64_t)diag[swz((int64_t)x)]) atomicOr(&bad, 1);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kWtStride * kWtStride; idx += 256) wts[idx] = w[idx];
+    for (int i = tid; i < kWtStride; i += 256) wts[kWtDeg + i] = deg[i];
+    if (tid == 0) wts[kWtOk] = bad ? 0 : 1;
+}
+
+// Cut table of a pass (layout in internal.h) for kernels of 2^tb threads whose
+// tiles hold 2^T amplitudes, evaluated in window s.  Blocks 0 .. gridDim.x - 2
+// write one tile row per thread; the last block writes the uniform and the
+// per-thread entries.
+__global__ void __launch_bounds__(256) cut_table_kernel(const int32_t *__restrict__ wts, int n, int c, int q0,
+                                                        int T, int tb, int s, int64_t ntiles,
+                                                        int32_t *__restrict__ ctab)
+{
+    __shared__ int32_t w[kWtStride * kWtStride];
+    __shared__ int32_t deg[kWtStride];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < n * kWtStride; i += 256) w[i] = wts[i];
+    for (int i = tid; i < kWtStride; i += 256) deg[i] = wts[kWtDeg + i];
+    __syncthreads();
+    const int rb = T - tb;
+    auto gbit = [&](int e) { return e < c ? e : q0 + (e - c); };  // tile bit -> global bit
+    // C of the bit set a (uint32 arithmetic, exact for C < 2^31)
+    auto cut = [&](uint64_t a) {
+        uint32_t cx = 0;
+        for (uint64_t m = a; m; m &= m - 1) {
+            const int i = __builtin_ctzll(m);
+            cx += (uint32_t)deg[i];
+            for (uint64_t b = m & (m - 1); b; b &= b - 1) cx -= 2u * (uint32_t)w[i * kWtStride + __builtin_ctzll(b)];
+        }
+        return cx;
+    };
+    if (blockIdx.x + 1 < gridDim.x) {
+        const int64_t tile = (int64_t)blockIdx.x * 256 + tid;
+        if (tile >= ntiles) return;
+        const uint64_t A = (uint64_t)tile_base(tile, c, q0, T - c);
+        int32_t *row = ctab + kCtTile + tile * 16;
+        row[0] = (int32_t)cut(A);
+        for (int e = 0; e < 15; ++e) {
+            uint32_t db = 0;
+            if (e < T) {
+                const int g = gbit(e);
+                for (uint64_t m = A; m; m &= m - 1) db += (uint32_t)w[g * kWtStride + __builtin_ctzll(m)];
+            }
+            row[1 + e] = (int32_t)db;
+        }
+        return;
+    }
+    if (tid < (1 << rb)) {
+        uint64_t D = 0;
+        for (int k = 0; k < rb; ++k)
+            if ((tid >> k) & 1) D |= 1ull << gbit(s + k);
+        ctab[kCtCreg + tid] = (int32_t)cut(D);
+    }
+    if (tid == 0) ctab[kCtValid] = wts[kWtOk];
+    for (int t = tid; t < (1 << tb); t += 256) {
+        const int et = win_elem(0, t, s, rb);
+        uint64_t B = 0;
+        for (int e = 0; e < T; ++e)
+            if ((et >> e) & 1) B |= 1ull << gbit(e);
+        int32_t *ent = ctab + kCtThr + t * 8;
+        ent[0] = (int32_t)cut(B);
+        for (int k = 0; k < 7; ++k) {
+            uint32_t dt = 0;
+            if (k < rb) {
+                const int g = gbit(s + k);
+                for (uint64_t m = B; m; m &= m - 1) dt += (uint32_t)w[g * kWtStride + __builtin_ctzll(m)];
+            }
+            ent[1 + k] = (int32_t)dt;
+        }
+    }
+}
+
 // ONE = false: persistent (one workgroup per CU), prefetching the next
 // tile's vectors, psi and lambda exchanged together through a two-tile LDS
 // buffer.  ONE = true: one tile per workgroup, no prefetch, one-tile LDS
@@ -131,6 +252,19 @@ __global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg 
 int phase_table_levels(int64_t W) { return phase_levels(W); }
 
 size_t pass_table_bytes() { return (size_t)kTabMax * sizeof(double2); }
+
+int64_t cut_table_entries(int n, int prec)
+{
+    const int T = tile_bits(prec);
+    return kCtTile + 16 * (n > T ? (int64_t)1 << (n - T) : 1);
+}
+
+hipError_t launch_cut_weights(const int32_t *diag, int n, int64_t W, int32_t *wts, hipStream_t st)
+{
+    if (n < 1 || n > kWtStride - 1 || !diag || !wts) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(cut_weights_kernel, dim3(1), dim3(256), 0, st, diag, n, W, wts);
+    return hipGetLastError();
+}
 
 int64_t pass_grid(int prec, int adjoint, int64_t ntiles)
 {
@@ -321,6 +455,20 @@ void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid
 }
 }  // namespace
 
+// Whether the kernel that launch_pass / launch_adjoint_pass pick for pp (kind
+// 0 = forward pass, 1 = turnaround, 2 = reverse pass) needs C_t and takes it
+// from a cut table: every forward and turnaround kernel does, and every
+// reverse kernel but the complex64 one-tile junction, which loads the
+// diagonal.
+bool pass_takes_cut_table(int prec, const PassProg &pp, int kind)
+{
+    if (kind == 0) return pp.has_phase || pp.readout;
+    if (kind == 1) return true;
+    if (!pp.has_phase) return false;
+    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
+    return adjoint_variant(prec, pp, 0, mode) != kAdjOneJunc;
+}
+
 // Grid of the kernel that launch_pass / launch_adjoint_pass pick for pp.
 int64_t tile_grid(int prec, int adjoint, const PassProg &pp)
 {
@@ -347,9 +495,34 @@ hipError_t launch_phase_table(int prec, const PassProg &pp, double f, hipStream_
 }
 }  // namespace
 
+namespace {
+// The window in which a pass evaluates C_t (the layout tiles.h loads the
+// diagonal in): kind 0 = forward pass (the phase layout, or the final one
+// for the readout), 1 = turnaround (final layout), 2 = reverse pass (phase
+// layout).
+int cut_window(const PassProg &pp, int kind)
+{
+    return kind == 0 ? (pp.has_phase ? pp.phase_win : pp.final_win) : kind == 1 ? pp.final_win : pp.phase_win;
+}
+
+// Write the pass's cut table (pp.ctab non-null only when the pass's kernel
+// takes one, see pass_takes_cut_table).
+hipError_t launch_cut_table(int prec, const PassProg &pp, int kind, int tb, hipStream_t st)
+{
+    if (!pp.ctab) return hipSuccess;
+    if (!pp.wts || pp.n > kWtStride - 1) return hipErrorInvalidValue;
+    const int T = tile_bits(prec);
+    const int64_t blocks = (pp.ntiles + 255) / 256 + 1;
+    hipLaunchKernelGGL(cut_table_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pp.wts, pp.n, pp.c, pp.q0, T, tb,
+                       cut_window(pp, kind), pp.ntiles, pp.ctab);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
     if (hipError_t e = launch_phase_table(prec, pp, pp.factor, st)) return e;
+    if (hipError_t e = launch_cut_table(prec, pp, 0, kFwdThreadBits, st)) return e;
     switch (tile_mode(pp, tile_bits(prec), kFwdThreadBits)) {
     case kModeTan: launch_pass_m<kModeTan>(prec, pp, grid, st); break;
     case kModeTanSym: launch_pass_m<kModeTanSym>(prec, pp, grid, st); break;
@@ -365,6 +538,7 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
     // (see rev_tile)
     const bool fold = !turnaround && mode != kModeGeneral && !pp.init;
     if (hipError_t e = launch_phase_table(prec, pp, fold ? pp.factor : 1.0, st)) return e;
+    if (hipError_t e = launch_cut_table(prec, pp, turnaround ? 1 : 2, kAdjThreadBits, st)) return e;
     switch (mode) {
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;

@@ -346,6 +346,55 @@ template <typename V, int T, int TB> struct TileCfg {
     static constexpr int NT = 1 << TB, RB = T - TB, NR = 1 << RB;
 };
 
+// C_t of the thread's registers in window s, evaluated from the pass's cut
+// table (see the cut-value notes in internal.h): the tile row and the
+// register terms are uniform (scalar loads), the thread's entries are two
+// vector loads, and each register then costs two integer adds.
+template <int T, int TB, int NR>
+__device__ __forceinline__ void cut_values(const PassProg &pp, int64_t tile, int s, int tid, int32_t (&C)[NR])
+{
+    constexpr int RB = T - TB;
+    const uint32_t *ct = reinterpret_cast<const uint32_t *>(pp.ctab);
+    const uint32_t *row = ct + kCtTile + tile * 16;
+    const uint32_t *ent = ct + kCtThr + tid * 8;
+    uint32_t c0 = row[0] + ent[0];
+#pragma unroll
+    for (int b = 0; b < TB; ++b) {
+        const uint32_t db = row[1 + (b < s ? b : b + RB)];  // thread bit b is tile bit b or b + RB
+        c0 -= ((tid >> b) & 1) ? 2u * db : 0u;
+    }
+    uint32_t a[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) a[k] = 0u - 2u * (row[1 + s + k] + ent[1 + k]);
+    uint32_t P[NR];
+    P[0] = c0;
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
+        const int t = 31 - __builtin_clz(r);
+        P[r] = P[r ^ (1 << t)] + a[t];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) C[r] = (int32_t)(P[r] + ct[kCtCreg + r]);
+}
+
+// C_t of the thread's registers in window s, loaded from the diagonal.
+template <int T, int TB, int NR>
+__device__ __forceinline__ void load_diag(const PassProg &pp, int s, int64_t base, int c, int q0, int tid,
+                                          int32_t (&C)[NR])
+{
+    for_each_reg<NR>(win_addr(tid, s, T - TB, base, c, q0), [&](int r, int64_t x) { C[r] = pp.diag[x]; });
+}
+
+// C_t of the thread's registers in window s: from the cut table when the pass
+// has a valid one, else loaded from the diagonal.
+template <int T, int TB, int NR>
+__device__ __forceinline__ void load_cut(const PassProg &pp, int64_t tile, int s, int64_t base, int c, int q0,
+                                         int tid, int32_t (&C)[NR])
+{
+    if (pp.ctab && pp.ctab[kCtValid]) cut_values<T, TB>(pp, tile, s, tid, C);
+    else load_diag<T, TB>(pp, s, base, c, q0, tid, C);
+}
+
 // Copy a phase table built in global memory into LDS.
 template <typename V>
 __device__ __forceinline__ void load_phase_table(V *tab, const V *src, int levels, int tid, int nthreads)
@@ -372,16 +421,14 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     const bool readout = KS ? (SH & kShReadout) != 0 : pp.readout != 0;
     const V *psi = reinterpret_cast<const V *>(pp.psi);
     V *out = reinterpret_cast<V *>(pp.psi_out);
-    const int32_t *diag = pp.diag;
     const bool need_diag = has_phase || readout;
     const int dwin = has_phase ? pp.phase_win : pp.final_win;
     const Geom g = geom_of(pp);
     const int64_t base = tile_base(tile, g.c, g.q0, g.m);
     V v[NR];
     int32_t dg[NR];
-    // the diagonal is loaded first so that its latency overlaps stage A
-    if (need_diag)
-        for_each_reg<NR>(win_addr(tid, opaque(dwin), RB, base, g.c, g.q0), [&](int r, int64_t x) { dg[r] = diag[x]; });
+    // C_t first, so that the latency of its loads overlaps stage A
+    if (need_diag) load_cut<T, TB>(pp, tile, opaque(dwin), base, g.c, g.q0, tid, dg);
     int cur = opaque(pp.load_win);
     if (init) {
 #pragma unroll
@@ -448,11 +495,9 @@ template <typename V, int T, int TB>
 __device__ __forceinline__ void turn_load_diag(const PassProg &pp, int64_t tile, int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                                int tid)
 {
-    using Cfg = TileCfg<V, T, TB>;
     const Geom gg = geom_of(pp);
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
-    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.final_win), Cfg::RB, base, gg.c, gg.q0),
-                          [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
+    load_cut<T, TB>(pp, tile, opaque(pp.final_win), base, gg.c, gg.q0, tid, dg);
 }
 
 template <typename V, int T, int TB, int MODE = kModeGeneral, bool PAIR = true, int K = 0>
@@ -518,11 +563,9 @@ template <typename V, int T, int TB>
 __device__ __forceinline__ void rev_load_diag(const PassProg &pp, int64_t tile, int32_t (&dg)[TileCfg<V, T, TB>::NR],
                                               int tid)
 {
-    using Cfg = TileCfg<V, T, TB>;
     const Geom gg = geom_of(pp);
     const int64_t base = tile_base(tile, gg.c, gg.q0, gg.m);
-    for_each_reg<Cfg::NR>(win_addr(tid, opaque(pp.phase_win), Cfg::RB, base, gg.c, gg.q0),
-                          [&](int r, int64_t g) { dg[r] = pp.diag[g]; });
+    load_cut<T, TB>(pp, tile, opaque(pp.phase_win), base, gg.c, gg.q0, tid, dg);
 }
 
 // Reverse pass, compute and store.  acc[0] += gx of the post layer, acc[1] +=
@@ -572,7 +615,9 @@ __device__ __forceinline__ void rev_tile(const PassProg &pp, int64_t tile, V (&p
         }
     }
     if (has_phase) {
-        if constexpr (LATE) rev_load_diag<V, T, TB>(pp, tile, dg, tid);
+        // (the late load reads the diagonal: within the one-tile junction's 128
+        // registers the cut table's terms would spill)
+        if constexpr (LATE) load_diag<T, TB>(pp, opaque(pp.phase_win), base, gg.c, gg.q0, tid, dg);
         // sum of (C - c) Im(conj(l) p) over the thread's amplitudes (c: see
         // turn_compute): each amplitude's Im(conj(l) p) in the state
         // precision, the products with C - c and their sum in FP64

@@ -132,6 +132,36 @@ def test_forward_random_angles_and_weight_ranges(precision, wmax, levels):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_diagonal_that_is_not_a_cut_is_read_entry_by_entry(precision):
+    """The tile passes evaluate C_t from the weights a cut diagonal encodes; a
+    diagonal that is not a cut function (here C_t + 1, nonzero at x = 0) must
+    be read entry by entry instead.  Each layer's phase exp(-i theta (W - 2C)/20)
+    then gains exp(i theta / 10), so the state gains exp(i sum(theta_zz) / 10),
+    <C> grows by 0.1 and the gradients are unchanged."""
+    n, p = 18, 3
+    w = workloads.complete_graph_tenths(n, 4)
+    g, b = oracle.ramp_midpoint(p, 0.6, 0.6)
+    tzz, tx = oracle.gate_angles(g, b)
+    sim = sim_for(w, precision)
+    e0, _ = sim.forward(tzz, tx)
+    psi0 = host_state(sim)
+    ea0, gzz0, gx0 = sim.adjoint(tzz, tx)
+    sim.diag += 1
+    e1, _ = sim.forward(tzz, tx)
+    psi1 = host_state(sim)
+    ea1, gzz1, gx1 = sim.adjoint(tzz, tx)
+    tol = 1e-5 if precision == "c64" else 1e-12
+    err = np.abs(psi1 - np.exp(1j * np.sum(tzz) / 10) * psi0).max() / np.abs(psi0).max()
+    scale = max(np.abs(gzz0).max(), np.abs(gx0).max())
+    gerr = max(np.abs(gzz1 - gzz0).max(), np.abs(gx1 - gx0).max()) / scale
+    say(f"  amplitudes rel {err:.2e}, <C> shift {e1 - e0:.12f}, gradient rel {gerr:.2e}")
+    assert err <= tol
+    assert abs(e1 - e0 - 0.1) <= tol * e0 and abs(ea1 - ea0 - 0.1) <= tol * e0
+    assert gerr <= (1e-4 if precision == "c64" else 1e-10)
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
 @pytest.mark.parametrize("n", [11, 16, 21])
 def test_separate_ops_match_oracle(n, precision):
     """qs_init_plus, qs_apply_cost_layer, qs_apply_mixer one by one."""

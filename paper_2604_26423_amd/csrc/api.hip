@@ -436,7 +436,7 @@ qs_status run_forward(qs_state s, const Circuit &cc, bool readout, const char *w
     if (s->n <= T) return run_small_forward(s, cc, readout, where);
 
     const std::vector<PassGeom> geo = plan_for(s);
-    std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
+    std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p, !s->sym);
     if (readout) ks.back().readout = 1;
     HIPCHK(ensure_partials(s, pass_grid(s->prec, 0, (int64_t)1 << (s->n - T))), where);
     if (qs_status st = prepare_cut(s, cc, where)) return st;
@@ -493,7 +493,7 @@ qs_status run_small_adjoint(qs_state s, const Circuit &cc, void *lam, const char
 int64_t forward_pass_count(qs_state s, int p)
 {
     if (s->n <= tile_bits(s->prec)) return 0;
-    return (int64_t)forward_specs((int)plan_for(s).size(), p).size();
+    return (int64_t)forward_specs((int)plan_for(s).size(), p, !s->sym).size();
 }
 
 // States a checkpointing adjoint keeps besides the state buffer: the outputs
@@ -518,7 +518,7 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     if (s->n <= T) return run_small_adjoint(s, cc, lam, where);
 
     const std::vector<PassGeom> geo = plan_for(s);
-    const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p);
+    const std::vector<KSpec> ks = forward_specs((int)geo.size(), cc.p, !s->sym);
     const int64_t ntiles = (int64_t)1 << (s->n - T);
     HIPCHK(ensure_partials(s, ntiles), where);  // no tile kernel has more workgroups than tiles
     if (qs_status st = prepare_cut(s, cc, where)) return st;
@@ -625,7 +625,7 @@ BatchSchedule build_batch_schedule(qs_batch b, const double *theta_zz, const dou
         const int32_t *diag = (const int32_t *)((char *)b->mem + b->off_diag[c]);
         const Circuit cc{diag, b->W[c], p, theta_zz + b->angle_off[c], theta_x + b->angle_off[c]};
         const std::vector<PassGeom> geo = plan_passes(n, b->prec);
-        const std::vector<KSpec> ks = forward_specs((int)geo.size(), p);
+        const std::vector<KSpec> ks = forward_specs((int)geo.size(), p, true);
         auto add = [&](const KSpec &k, int kind) {
             BatchStep s{};
             s.pp = make_prog_raw(psi, n, b->prec, nullptr, geo[k.pass], k, cc, kBatchThreadBits);

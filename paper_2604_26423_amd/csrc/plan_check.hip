@@ -154,11 +154,11 @@ int check_tile_maps(Report &R, int n, int T, int tb, const PassGeom &g, const Wi
     return 0;
 }
 
-int check_schedule(Report &R, int P, int p)
+int check_schedule(Report &R, int P, int p, bool mid)
 {
     // walk the kernels in order and track, per layer, how many passes of the
     // mixer have run and whether the phase has run
-    const std::vector<KSpec> ks = forward_specs(P, p);
+    const std::vector<KSpec> ks = forward_specs(P, p, mid);
     std::vector<int> phase_done(p, 0), mixer_count(p, 0);
     std::vector<std::vector<int>> pass_seen(p, std::vector<int>(P, 0));
     if (ks.empty() || !ks[0].init || ks[0].phase != 0) return R.fail("first kernel must start from |+> with phase 0");
@@ -218,7 +218,7 @@ int check_sym(Report &R, int n, int prec, int p)
             if (check_tile_maps(R, N, T, tb, g, seq, 3)) return 1;
         }
     }
-    return check_schedule(R, (int)geo.size(), p);
+    return check_schedule(R, (int)geo.size(), p, false);
 }
 }  // namespace
 
@@ -271,7 +271,7 @@ extern "C" int qs_plan_check(int n, int prec_arg, int p, char *msg, size_t msg_l
             if (check_tile_maps(R, n, T, tb, g, seq, 3)) return 1;
         }
     }
-    if (check_schedule(R, (int)geo.size(), p)) return 1;
+    if (check_schedule(R, (int)geo.size(), p, true)) return 1;
     // the XCD renumbering is a bijection whenever it is enabled (grid % 8 == 0)
     const int64_t grid = (int64_t)1 << (n - T);
     if (grid % 8 == 0 && grid <= (1 << 22)) {

@@ -207,6 +207,26 @@ RxStage rx_stage(double theta, int m, double *factor)
     return st;
 }
 
+// Gradient scales of a reverse stage over the window sequence w of a kernel
+// with 2^tb threads (RxStage::wsc): the windows are undone from the last, each
+// undoing the factors of the stage it holds that no later window held.
+void stage_scales(RxStage &st, const WinSeq &w, uint32_t targets, uint32_t pairs, int T, int tb)
+{
+    const int rb = T - tb;
+    const double c2 = st.tan ? st.c * st.c : 1.0;
+    double sc = 1.0;
+    uint32_t done = 0, pdone = 0;
+    for (int i = 0; i < kMaxWindows; ++i) st.wsc[i] = 1.0;
+    for (int i = std::min(w.cnt, kMaxWindows) - 1; i >= 0; --i) {
+        const uint32_t mask = targets & (((1u << rb) - 1u) << w.s[i]) & ~done;
+        const uint32_t pm = pairs & (((1u << (rb - 1)) - 1u) << w.s[i]) & ~pdone;
+        st.wsc[i] = sc;
+        for (int b = __builtin_popcount(mask) + __builtin_popcount(pm); b > 0; --b) sc *= c2;
+        done |= mask;
+        pdone |= pm;
+    }
+}
+
 // Last window of a sequence.  A sequence longer than kMaxWindows (flagged by
 // plan_windows) never occurs for a supported n -- qs_plan_check verifies every
 // plan -- and the clamp keeps the read inside the array regardless.
@@ -248,6 +268,8 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
         pp.B = plan_windows(tb, g.targets, g.pairs, T, tb);
     }
     if (pp.has_post) pp.post = rx_stage(cc.tx[k.post], pp.ntargets, &pp.fpost);
+    if (pp.has_pre) stage_scales(pp.pre, pp.A, g.targets, g.pairs, T, tb);
+    if (pp.has_post) stage_scales(pp.post, pp.B, g.targets, g.pairs, T, tb);
     pp.factor = pp.fpre * pp.fpost;
     pp.phase_win = pp.has_pre ? last_window(pp.A) : pp.load_win;
     pp.final_win = last_window(pp.B);

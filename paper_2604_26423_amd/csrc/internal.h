@@ -39,6 +39,12 @@ struct WinSeq {
 struct RxStage {
     double c, s, u;
     int tan;
+    // Reverse stage: the gradient terms of window i (of the stage's window
+    // sequence, walked from the last) are scaled by wsc[i] = cos(theta/2)^(2j),
+    // j the factors undone before it (tangent form; 1 in the direct form).
+    // Evaluated on the host: as uniform FP64 values they would take vector
+    // registers for the whole pass.
+    double wsc[kMaxWindows];
 };
 
 struct PassProg {

@@ -282,14 +282,13 @@ __device__ __forceinline__ void run_stage(V (&v)[NR], V *lds, const WinSeq &seq,
 // Reverse stage on psi and lambda together: windows in reverse order; for each
 // factor accumulate Im <lam| X.. |psi> (invariant under the stage applied to
 // both), then apply RX(-theta) to both.  In tangent form both vectors carry
-// 1/cos^j after j factors, so the terms are rescaled by cos^(2j).
+// 1/cos^j after j factors, so the terms of window i are rescaled by
+// st.wsc[i] = cos^(2j) (evaluated on the host).
 template <int RB, int MODE, bool PAIR, int TAIL = 0, typename V, int NR>
 __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, const WinSeq &seq,
                                             uint32_t targets, uint32_t pairs, const RxStage &st, int &cur, int tid,
                                             double &gx)
 {
-    double sc = 1.0;
-    const double c2 = st.tan ? st.c * st.c : 1.0;
     if constexpr (TAIL != 0) {
         // windows in reverse order; all but the last visited (index 0) full
         static_assert(MODE == kModeTan, "compile-time tails are for single-factor tangent-form stages");
@@ -307,13 +306,12 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
         };
         for (int i = seq.cnt - 1; i > 0; --i) {
             if (i < seq.cnt - 1) to(opaque(seq.s[i]));
-            gx += sc * imx_reg_const<FULL>(l, p);
+            gx += st.wsc[i] * imx_reg_const<FULL>(l, p);
             rxt_reg_const<FULL>(p, u);
             rxt_reg_const<FULL>(l, u);
-            for (int b = 0; b < RB; ++b) sc *= c2;
         }
         if (seq.cnt > 1) to(opaque(seq.s[0]));  // (opaque: see run_stage)
-        gx += sc * imx_reg_const<LAST>(l, p);
+        gx += st.wsc[0] * imx_reg_const<LAST>(l, p);
         rxt_reg_const<LAST>(p, u);
         rxt_reg_const<LAST>(l, u);
         return;
@@ -332,10 +330,9 @@ __device__ __forceinline__ void unrun_stage(V (&p)[NR], V (&l)[NR], V *lds, cons
         }
         const uint32_t mask = win_singles<RB>(targets, w) & ~done;
         const uint32_t pm = win_pairs<RB>(pairs, w) & ~pdone;
-        gx += sc * imx_window<MODE>(l, p, mask >> w, pm >> w);
+        gx += st.wsc[i] * imx_window<MODE>(l, p, mask >> w, pm >> w);
         apply_window<MODE>(p, mask >> w, pm >> w, st, -1);
         apply_window<MODE>(l, mask >> w, pm >> w, st, -1);
-        for (int b = __builtin_popcount(mask) + __builtin_popcount(pm); b > 0; --b) sc *= c2;
         done |= mask;
         pdone |= pm;
     }

@@ -1,10 +1,13 @@
 /*
- * qs_debug.h -- host-only diagnostics of libqs.  Nothing here touches a GPU.
+ * qs_debug.h -- host-only diagnostics and test controls of libqs.  Nothing
+ * here touches a GPU.
  */
 #ifndef QS_DEBUG_H
 #define QS_DEBUG_H
 
 #include <stddef.h>
+
+#include "qs.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -47,6 +50,19 @@ int qs_plan_check(int n, int prec, int p, char *msg, size_t msg_len);
  */
 struct qs_circuit;
 int qs_batch_plan_check(int count, const struct qs_circuit *circuits, int prec, char *msg, size_t msg_len);
+
+/*
+ * How the tile passes of a full-layout state s obtain the cut value C_t[x] of
+ * eq. (6) in the calls that follow (qs_forward, qs_adjoint_grad,
+ * qs_adjoint_grad_store): 0 = automatic (evaluated in registers from the
+ * weights the diagonal encodes for n >= 28 qubits, read from the diagonal
+ * below), 1 = evaluated in registers at any size, 2 = read from the diagonal
+ * at any size.  The two ways give the same integers, so results are
+ * bit-identical across modes; the mode changes only speed.  For tests and
+ * measurements.  The complement-symmetric layout always reads its diagonal.
+ * Errors: QS_ERR_ARG (mode outside 0..2, null state).
+ */
+qs_status qs_debug_set_cut_mode(qs_state s, int mode);
 
 #ifdef __cplusplus
 }

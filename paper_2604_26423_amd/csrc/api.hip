@@ -120,6 +120,8 @@ struct qs_state_s {
     bool own = false;
     hipStream_t stream = nullptr;
     DevBuf partials, tmp, results, sample, shots_out, lambda, hist, xfer, tab, wts, ctab;
+    int cut_mode = 0;     // qs_debug_set_cut_mode
+    bool cut_on = false;  // this call's passes take cut tables
     bool prof = false;
     std::vector<ProfRec> recs;
 };
@@ -286,7 +288,7 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
 PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit &cc, int tb, int kind = 0)
 {
     PassProg pp = make_prog_raw(s->psi, s->n, s->prec, (double *)s->partials.p, g, k, cc, tb, s->sym);
-    if (!s->sym && s->ctab.p && s->wts.p && pass_takes_cut_table(s->prec, pp, kind)) {
+    if (s->cut_on && pass_takes_cut_table(s->prec, pp, kind)) {
         pp.ctab = (int32_t *)s->ctab.p;
         pp.wts = (const int32_t *)s->wts.p;
     }
@@ -294,14 +296,18 @@ PassProg make_prog(qs_state s, const PassGeom &g, const KSpec &k, const Circuit 
 }
 
 // Tile passes of the full layout evaluate C_t in registers (see the cut-value
-// notes in internal.h): recover the weights from the diagonal of this call
-// and size the per-pass cut table.
+// notes in internal.h) from n = kCutMinQubits on, or as qs_debug_set_cut_mode
+// says: recover the weights from the diagonal of this call and size the
+// per-pass cut table.
 qs_status prepare_cut(qs_state s, const Circuit &cc, const char *where)
 {
+    s->cut_on = false;
     if (s->sym || s->n <= tile_bits(s->prec)) return QS_OK;
+    if (s->cut_mode == 2 || (s->cut_mode == 0 && s->n < kCutMinQubits)) return QS_OK;
     HIPCHK(s->wts.ensure((size_t)kWtSize * sizeof(int32_t)), where);
     HIPCHK(s->ctab.ensure((size_t)cut_table_entries(s->n, s->prec) * sizeof(int32_t)), where);
     HIPCHK(launch_cut_weights(cc.diag, s->n, cc.W, (int32_t *)s->wts.p, s->stream), where);
+    s->cut_on = true;
     return QS_OK;
 }
 
@@ -1285,6 +1291,14 @@ qs_status qs_adjoint_grad_store(qs_state s, const int32_t *diag_dev, int64_t w_t
 {
     return adjoint_entry(s, diag_dev, w_total_tenths, p, theta_zz, theta_x, ckpt_buf, ckpt_bytes, true,
                          lambda_buf, lambda_bytes, exp_c, d_theta_zz, d_theta_x, "qs_adjoint_grad_store");
+}
+
+qs_status qs_debug_set_cut_mode(qs_state s, int mode)
+{
+    if (qs_status st = check_state(s)) return st;
+    if (mode < 0 || mode > 2) return fail(QS_ERR_ARG, "cut mode %d (0 automatic, 1 registers, 2 diagonal)", mode);
+    s->cut_mode = mode;
+    return QS_OK;
 }
 
 qs_status qs_profile(qs_state s, int enable)

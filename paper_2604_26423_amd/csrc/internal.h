@@ -114,6 +114,11 @@ constexpr int kCtValid = 32;                      // copy of the weights' ok fla
 constexpr int kCtThr = 64;                        // per thread: C(B_t), Dt_0 .. Dt_{RB-1}, 8 entries
 constexpr int kCtTile = kCtThr + 8 * 512;         // per tile: C(A), Db_0 .. Db_{T-1}, 16 entries
 constexpr int kCtSamples = 1024;                  // diagonal entries checked against the weights
+// Smallest state (qubits, full layout) whose passes evaluate C_t in registers
+// by default: the weights and tables cost ~0.1 ms per call, which the saved
+// diagonal reads repay from n = 28 on (complex64 forward, p = 3: 1.8x slower
+// at n = 16..22, even at n = 27, 3% faster at n = 28..30).
+constexpr int kCutMinQubits = 28;
 
 // ---- index maps of a tile pass (host and device) ----
 

@@ -42,7 +42,7 @@ EXPORTS = ["qs_last_error", "qs_version", "qs_state_bytes", "qs_alloc", "qs_free
            "qs_profile", "qs_profile_read",
            "qs_plan_check", "qs_batch_plan_check", "qs_batch_create", "qs_batch_info", "qs_batch_forward_grad",
            "qs_batch_free", "qs_noise_create", "qs_noise_info", "qs_noise_run", "qs_noise_free",
-           "qs_bandwidth_probe", "qs_cost_diagonal_noalloc"]
+           "qs_bandwidth_probe", "qs_cost_diagonal_noalloc", "qs_debug_set_cut_mode"]
 QS_BATCH_MAX_QUBITS = 30
 QS_NOISE_MAX_QUBITS = 12
 QS_NOISE_MAX_LAYERS = 4096
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "qs_profile": ([vp, i32], i32),
         "qs_profile_read": ([vp, i32, _c_i64_p, _c_dbl_p, _c_dbl_p], i32),
         "qs_plan_check": ([i32, i32, i32, ctypes.c_char_p, sz], i32),
+        "qs_debug_set_cut_mode": ([vp, i32], i32),
         "qs_batch_plan_check": ([i32, vp, i32, ctypes.c_char_p, sz], i32),
         "qs_batch_create": ([i32, vp, i32, vp, ctypes.POINTER(vp)], i32),
         "qs_batch_info": ([vp, i32, _c_i64_p, _c_i32_p, ctypes.POINTER(vp), ctypes.POINTER(vp)], i32),
@@ -347,6 +348,14 @@ def qs_adjoint_ckpt_bytes(s, p: int) -> int:
     b = ctypes.c_size_t()
     _check(lib().qs_adjoint_ckpt_bytes(s, int(p), ctypes.byref(b)))
     return int(b.value)
+
+
+CUT_MODES = {"auto": 0, "registers": 1, "diagonal": 2}
+
+
+def qs_debug_set_cut_mode(s, mode) -> None:
+    """How the tile passes get C_t: "auto", "registers" or "diagonal" (or 0, 1, 2)."""
+    _check(lib().qs_debug_set_cut_mode(s, CUT_MODES[mode] if isinstance(mode, str) else int(mode)))
 
 
 def qs_profile(s, enable: bool) -> None:

@@ -88,6 +88,11 @@ def test_entry_point_validation(fake_state):
     expect_status(qs.QS_ERR_ARG, qs.qs_adjoint_grad, s, diag, 100, [0.1], [0.2], FAKE + (1 << 30), 16)
     expect_status(qs.QS_ERR_ARG, qs.qs_profile_read, s, 99)
     assert "null state" in expect_status(qs.QS_ERR_ARG, qs.qs_init_plus, None)
+    for mode in ("auto", "registers", "diagonal", 0, 1, 2):
+        qs.qs_debug_set_cut_mode(s, mode)
+    expect_status(qs.QS_ERR_ARG, qs.qs_debug_set_cut_mode, s, 3)
+    expect_status(qs.QS_ERR_ARG, qs.qs_debug_set_cut_mode, s, -1)
+    expect_status(qs.QS_ERR_ARG, qs.qs_debug_set_cut_mode, None, 0)
 
 
 def test_store_mode_checkpoint_size_and_validation(fake_state):

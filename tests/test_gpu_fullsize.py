@@ -181,6 +181,28 @@ def test_n32_c64_vs_c128_and_single_layer_closed_form():
     release(s128)
 
 
+def test_n32_cut_in_registers_matches_diagonal_bit_for_bit():
+    """At n = 32 the passes evaluate C_t in registers by default; reading the
+    diagonal instead must give the same state, <C> and gradient bit for bit."""
+    from paper_2604_26423_amd import qs
+    run = workloads.LARGE
+    w = run.weights()
+    tzz, tx = oracle.gate_angles(*oracle.ramp_midpoint(3, run.delta_gamma, run.delta_beta))
+    s = sim(w, "c64")
+    e1, n1 = s.forward(tzz, tx)
+    ref = s.psi.clone()
+    g1 = s.adjoint(tzz, tx)
+    qs.qs_debug_set_cut_mode(s.handle, "diagonal")
+    e2, n2 = s.forward(tzz, tx)
+    same = all(torch.equal(a.view(torch.float32), b.view(torch.float32)) for a, b in zip(chunks(ref), chunks(s.psi)))
+    del ref
+    torch.cuda.empty_cache()
+    g2 = s.adjoint(tzz, tx)
+    say(f"  <C> {e1:.12f} / {e2:.12f}, states equal {same}, gradients equal {np.array_equal(g1[1], g2[1])}")
+    assert same and e1 == e2 and n1 == n2
+    assert g1[0] == g2[0] and np.array_equal(g1[1], g2[1]) and np.array_equal(g1[2], g2[2])
+
+
 def test_n32_single_layers_closed_forms():
     """One cost layer on |+>: a_x = 2^(-n/2) exp(-i theta (W - 2C_x)/20).
     One mixer on |0>: a_y = cos(t/2)^(n-|y|) (-i sin(t/2))^|y|."""

@@ -132,6 +132,34 @@ def test_forward_random_angles_and_weight_ranges(precision, wmax, levels):
 
 
 @pytest.mark.parametrize("precision", ["c64", "c128"])
+@pytest.mark.parametrize("n,p", [(14, 3), (17, 2), (21, 4), (24, 3)])
+def test_cut_in_registers_and_from_the_diagonal_bit_identical(n, p, precision):
+    """The tile passes either evaluate C_t in registers from the weights the
+    diagonal encodes or read the diagonal; both give the same integers, so the
+    state, <C> and the gradients (both adjoint modes) must agree bit for bit.
+    (The diagonal path is held to the oracle by the tests above.)"""
+    from paper_2604_26423_amd import qs
+    w = workloads.complete_graph_tenths(n, 3 * n + p)
+    g, b = oracle.ramp_midpoint(p, 0.6, 0.6)
+    tzz, tx = oracle.gate_angles(g, b)
+    sim = sim_for(w, precision)
+    res = {}
+    for mode in ("diagonal", "registers"):
+        qs.qs_debug_set_cut_mode(sim.handle, mode)
+        e, nrm = sim.forward(tzz, tx)
+        psi = sim.amplitudes().clone()
+        grads = [sim.adjoint(tzz, tx, mode=m) for m in ("uncompute", "store")]
+        res[mode] = (e, nrm, psi, grads)
+    (e0, n0, p0, g0), (e1, n1, p1, g1) = res["diagonal"], res["registers"]
+    assert e0 == e1 and n0 == n1
+    assert torch.equal(p0.view(torch.float32 if precision == "c64" else torch.float64),
+                       p1.view(torch.float32 if precision == "c64" else torch.float64))
+    for a, b in zip(g0, g1):
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "c128"])
 def test_diagonal_that_is_not_a_cut_is_read_entry_by_entry(precision):
     """The tile passes evaluate C_t from the weights a cut diagonal encodes; a
     diagonal that is not a cut function (here C_t + 1, nonzero at x = 0) must
@@ -143,6 +171,8 @@ def test_diagonal_that_is_not_a_cut_is_read_entry_by_entry(precision):
     g, b = oracle.ramp_midpoint(p, 0.6, 0.6)
     tzz, tx = oracle.gate_angles(g, b)
     sim = sim_for(w, precision)
+    from paper_2604_26423_amd import qs
+    qs.qs_debug_set_cut_mode(sim.handle, "registers")   # the in-register path at this size too
     e0, _ = sim.forward(tzz, tx)
     psi0 = host_state(sim)
     ea0, gzz0, gx0 = sim.adjoint(tzz, tx)

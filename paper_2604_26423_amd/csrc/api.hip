@@ -584,6 +584,8 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     for (int i = (int)ks.size() - 2; i >= 0; --i) {
         const KSpec &k = ks[i];
         PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 2);
+        const int tb = adjoint_thread_bits(s->prec, pp, 0);
+        if (tb != kAdjThreadBits) pp = make_prog(s, geo[k.pass], k, cc, tb, 2);
         pp.lam = lam;
         pp.load_win = pp.final_win;
         if (ckpt) {

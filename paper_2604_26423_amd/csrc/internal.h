@@ -10,6 +10,7 @@ namespace qs {
 constexpr int kThreads = 256;         // threads per workgroup of the elementwise kernels
 constexpr int kFwdThreadBits = 8;     // forward tile kernels: 256 threads
 constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
+constexpr int kAdjJuncThreadBits = 8; // ... but the complex64 one-tile reverse junction: 256
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
 constexpr int kMaxWindows = 8;        // register windows per butterfly stage
@@ -198,6 +199,9 @@ __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_
 
 // Host-side launchers (one per kernel family); all return hipError_t.
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
+// Threads (log2) of the reverse kernel (turnaround: 1) that launch_adjoint_pass
+// picks for pp; its windows must be planned for them.
+int adjoint_thread_bits(int prec, const PassProg &pp, int turnaround);
 // Bytes of the device buffer PassProg::tab points to (any precision).
 size_t pass_table_bytes();
 // Recover the weights of the cut function in diag (2^n entries, full layout)

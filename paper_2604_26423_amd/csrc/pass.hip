@@ -1,6 +1,6 @@
 // Tile-pass kernels of a single circuit: the fused layer passes of the
 // forward circuit and of the adjoint (reverse) sweep.  The per-tile work is in
-// tiles.h; these kernels build the workgroup's phase table, walk tiles and
+// tiles.h; these kernels copy the pass's phase table into LDS, walk tiles and
 // reduce the workgroup's partial sums.
 //
 // Forward passes launch one workgroup per tile.  The complex64 adjoint
@@ -171,16 +171,17 @@ __global__ void __launch_bounds__(256) cut_table_kernel(const int32_t *__restric
 // ONE = false: persistent (one workgroup per CU), prefetching the next
 // tile's vectors, psi and lambda exchanged together through a two-tile LDS
 // buffer.  ONE = true: one tile per workgroup, no prefetch, one-tile LDS
-// buffer, at most 128 registers (launch bounds), so that two workgroups share
-// a CU and overlap each other's memory and compute phases.
+// buffer, registers for two workgroups per CU (launch bounds: 128 with 512
+// threads, 256 with 256 threads), so that two workgroups share a CU and
+// overlap each other's memory and compute phases.
 template <typename V, int T, int TB, bool turnaround, int MODE, int SH, bool ONE, int K = 0>
-__global__ void __launch_bounds__(1 << TB, ONE ? 4 : 1) adjoint_kernel(PassProg pp)
+__global__ void __launch_bounds__(1 << TB, ONE ? (TB == 9 ? 4 : 2) : 1) adjoint_kernel(PassProg pp)
 {
     using Cfg = TileCfg<V, T, TB>;
     constexpr int NT = Cfg::NT, NR = Cfg::NR;
     constexpr bool PAIR = !ONE;
     constexpr bool PREFETCH = !ONE;
-    static_assert(TB == 9, "exchange2 assumes 512-thread tiles");
+    static_assert(ONE || TB == 9, "exchange2 assumes 512-thread tiles");
     __shared__ V lds[(PAIR ? 2 : 1) << T];
     __shared__ V tab[kTabMax];
     __shared__ double red[kSlots * (NT / 64)];
@@ -379,10 +380,9 @@ void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
     }
 }
 
-template <int MODE, bool TURN, int SH, bool ONE>
+template <int MODE, bool TURN, int SH, bool ONE, int AT = kAdjThreadBits>
 void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
-    constexpr int AT = kAdjThreadBits;
     const dim3 g((unsigned)grid), b(1 << AT);
     if (prec == 0) hipLaunchKernelGGL((adjoint_kernel<float2, kTileBitsC64, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
     else hipLaunchKernelGGL((adjoint_kernel<double2, kTileBitsC128, AT, TURN, MODE, SH, ONE>), g, b, 0, st, pp);
@@ -446,7 +446,13 @@ void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid
     case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true>(prec, pp, grid, st); break;
     case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true>(prec, pp, grid, st); break;
     case kAdjOneFirst: launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost, true>(prec, pp, grid, st); break;
-    case kAdjOneJunc: launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true>(prec, pp, grid, st); break;
+    case kAdjOneJunc:
+        // complex64, full layout: 256 threads of 32 amplitudes per vector (see
+        // adjoint_thread_bits)
+        if (adjoint_thread_bits(prec, pp, 0) == kAdjJuncThreadBits)
+            launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true, kAdjJuncThreadBits>(prec, pp, grid, st);
+        else launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true>(prec, pp, grid, st);
+        break;
     default:
         if (turnaround) launch_adjoint_s<MODE, true, -1, false>(prec, pp, grid, st);
         else launch_adjoint_s<MODE, false, -1, false>(prec, pp, grid, st);
@@ -467,6 +473,20 @@ bool pass_takes_cut_table(int prec, const PassProg &pp, int kind)
     if (!pp.has_phase) return false;
     const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
     return adjoint_variant(prec, pp, 0, mode) != kAdjOneJunc;
+}
+
+// Threads (log2) of the reverse kernel picked for pp, for which its windows
+// must be planned: the complex64 one-tile junction of the full layout runs
+// 256 threads of 32 amplitudes per vector (windows of 5 bits: two per stage
+// instead of three, so half the exchanges of 512 threads, at 246 registers
+// for two workgroups per CU); every other adjoint kernel 512 (the
+// complement-symmetric layout's two-bit factors keep the 512-thread windows
+// its stage code was checked for).
+int adjoint_thread_bits(int prec, const PassProg &pp, int turnaround)
+{
+    if (turnaround || prec != 0 || pp.pairs) return kAdjThreadBits;
+    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
+    return adjoint_variant(prec, pp, 0, mode) == kAdjOneJunc ? kAdjJuncThreadBits : kAdjThreadBits;
 }
 
 // Grid of the kernel that launch_pass / launch_adjoint_pass pick for pp.
@@ -538,7 +558,8 @@ hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int
     // (see rev_tile)
     const bool fold = !turnaround && mode != kModeGeneral && !pp.init;
     if (hipError_t e = launch_phase_table(prec, pp, fold ? pp.factor : 1.0, st)) return e;
-    if (hipError_t e = launch_cut_table(prec, pp, turnaround ? 1 : 2, kAdjThreadBits, st)) return e;
+    if (hipError_t e = launch_cut_table(prec, pp, turnaround ? 1 : 2, adjoint_thread_bits(prec, pp, turnaround), st))
+        return e;
     switch (mode) {
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;

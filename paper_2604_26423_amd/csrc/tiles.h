@@ -475,7 +475,7 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
 // bitstrings) the terms, and with them the rounding of a complex64 sweep, are
 // several times smaller than with c = 0, where they are of the size of <C>
 // and cancel to a gradient of order 1.  Split
-// into loads (psi in the load layout, the diagonal in the final layout) and
+// into loads (psi in the load layout, C_t in the final layout) and
 // the rest, so that a persistent kernel can load the next tile early.
 template <typename V, int T, int TB>
 __device__ __forceinline__ void turn_load(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR], int tid)
@@ -513,7 +513,7 @@ __device__ __forceinline__ void turn_compute(const PassProg &pp, int64_t tile, V
     int cur = opaque(pp.load_win);
     // K > 0: the stage forward ends in +K, its reverse in -K (fixed at compile time)
     run_stage<RB, MODE, K>(p, lds, pp.B, pp.targets, pp.pairs, pp.post, cur, tid);
-    // cur is now the final layout, the one the diagonal was loaded in
+    // cur is now the final layout, the one C_t was obtained in
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         const int32_t C = dg[r];
@@ -540,7 +540,7 @@ __device__ __forceinline__ void turn_tile(const PassProg &pp, int64_t tile, V *l
 }
 
 // Reverse pass, loads: psi and lambda of a tile in the pass's load layout, and
-// the diagonal in the layout of the phase step.
+// C_t in the layout of the phase step.
 template <typename V, int T, int TB>
 __device__ __forceinline__ void rev_load_vectors(const PassProg &pp, int64_t tile, V (&p)[TileCfg<V, T, TB>::NR],
                                                  V (&l)[TileCfg<V, T, TB>::NR], int tid)

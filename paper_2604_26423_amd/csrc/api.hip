@@ -573,6 +573,8 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     {
         const KSpec &k = ks.back();
         PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 1);
+        const int tb = adjoint_thread_bits(s->prec, pp, 1);
+        if (tb != kAdjThreadBits) pp = make_prog(s, geo[k.pass], k, cc, tb, 1);
         pp.lam = lam;
         if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_TURNAROUND, dim * (2.0 * ab + (pp.ctab ? 0.0 : 4.0)),
                                         &grid, where))

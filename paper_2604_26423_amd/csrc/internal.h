@@ -10,7 +10,7 @@ namespace qs {
 constexpr int kThreads = 256;         // threads per workgroup of the elementwise kernels
 constexpr int kFwdThreadBits = 8;     // forward tile kernels: 256 threads
 constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
-constexpr int kAdjJuncThreadBits = 8; // ... but the complex64 one-tile reverse junction: 256
+constexpr int kAdjOneThreadBits = 8;  // ... but the complex64 one-tile kernels of the full layout: 256
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
 constexpr int kMaxWindows = 8;        // register windows per butterfly stage

@@ -389,10 +389,9 @@ void launch_adjoint_s(int prec, const PassProg &pp, int64_t grid, hipStream_t st
 }
 
 // complex64 one-tile tangent-form kernels: the instantiation for the pass's tail
-template <bool TURN, int SH>
+template <bool TURN, int SH, int AT>
 void launch_adjoint_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
-    constexpr int AT = kAdjThreadBits;
     const int k = prec == 0 ? tail_k(pp, kTileBitsC64, AT, TURN ? 1 : 2) : 0;
     const dim3 g((unsigned)grid), b(1 << AT);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, 0, st, pp); };
@@ -401,7 +400,7 @@ void launch_adjoint_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st
     case 2: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 2>); break;
     case 3: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 3>); break;
     case 4: go(adjoint_kernel<float2, kTileBitsC64, AT, TURN, kModeTan, SH, true, 4>); break;
-    default: launch_adjoint_s<kModeTan, TURN, SH, true>(prec, pp, grid, st); break;
+    default: launch_adjoint_s<kModeTan, TURN, SH, true, AT>(prec, pp, grid, st); break;
     }
 }
 
@@ -427,37 +426,43 @@ int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
     }
 }
 
-template <int MODE>
-void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
+// AT: thread bits of the one-tile kernels (adjoint_thread_bits); the
+// persistent kernels are 512-thread only.
+template <int MODE, int AT>
+void launch_adjoint_m_at(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
     if constexpr (MODE == kModeTan) {
         if (prec == 0) {
             switch (adjoint_variant(prec, pp, turnaround, MODE)) {
-            case kAdjOneTurn: launch_adjoint_k<true, -1>(prec, pp, grid, st); return;
+            case kAdjOneTurn: launch_adjoint_k<true, -1, AT>(prec, pp, grid, st); return;
             // (the reverse of a plain pass and the reverse junction keep runtime
-            // masks: with compile-time tails their code needs more than the 128
-            // registers of two workgroups per CU and spills)
-            case kAdjOneFirst: launch_adjoint_k<false, kShInit | kShPhase | kShPost>(prec, pp, grid, st); return;
+            // masks: with compile-time tails their 512-thread code needs more
+            // than the 128 registers of two workgroups per CU and spills)
+            case kAdjOneFirst: launch_adjoint_k<false, kShInit | kShPhase | kShPost, AT>(prec, pp, grid, st); return;
             default: break;
             }
         }
     }
     switch (adjoint_variant(prec, pp, turnaround, MODE)) {
-    case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true>(prec, pp, grid, st); break;
-    case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true>(prec, pp, grid, st); break;
-    case kAdjOneFirst: launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost, true>(prec, pp, grid, st); break;
-    case kAdjOneJunc:
-        // complex64, full layout: 256 threads of 32 amplitudes per vector (see
-        // adjoint_thread_bits)
-        if (adjoint_thread_bits(prec, pp, 0) == kAdjJuncThreadBits)
-            launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true, kAdjJuncThreadBits>(prec, pp, grid, st);
-        else launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true>(prec, pp, grid, st);
-        break;
+    case kAdjOneTurn: launch_adjoint_s<MODE, true, -1, true, AT>(prec, pp, grid, st); break;
+    case kAdjOnePlain: launch_adjoint_s<MODE, false, kShPost, true, AT>(prec, pp, grid, st); break;
+    case kAdjOneFirst: launch_adjoint_s<MODE, false, kShInit | kShPhase | kShPost, true, AT>(prec, pp, grid, st); break;
+    case kAdjOneJunc: launch_adjoint_s<MODE, false, kShPre | kShPhase | kShPost, true, AT>(prec, pp, grid, st); break;
     default:
-        if (turnaround) launch_adjoint_s<MODE, true, -1, false>(prec, pp, grid, st);
-        else launch_adjoint_s<MODE, false, -1, false>(prec, pp, grid, st);
+        if constexpr (AT == kAdjThreadBits) {
+            if (turnaround) launch_adjoint_s<MODE, true, -1, false>(prec, pp, grid, st);
+            else launch_adjoint_s<MODE, false, -1, false>(prec, pp, grid, st);
+        }
         break;
     }
+}
+
+template <int MODE>
+void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
+{
+    if (adjoint_thread_bits(prec, pp, turnaround) == kAdjOneThreadBits)
+        launch_adjoint_m_at<MODE, kAdjOneThreadBits>(prec, pp, turnaround, grid, st);
+    else launch_adjoint_m_at<MODE, kAdjThreadBits>(prec, pp, turnaround, grid, st);
 }
 }  // namespace
 
@@ -475,18 +480,20 @@ bool pass_takes_cut_table(int prec, const PassProg &pp, int kind)
     return adjoint_variant(prec, pp, 0, mode) != kAdjOneJunc;
 }
 
-// Threads (log2) of the reverse kernel picked for pp, for which its windows
-// must be planned: the complex64 one-tile junction of the full layout runs
-// 256 threads of 32 amplitudes per vector (windows of 5 bits: two per stage
-// instead of three, so half the exchanges of 512 threads, at 246 registers
-// for two workgroups per CU); every other adjoint kernel 512 (the
-// complement-symmetric layout's two-bit factors keep the 512-thread windows
-// its stage code was checked for).
+// Threads (log2) of the adjoint kernel picked for pp, for which its windows
+// must be planned: the complex64 one-tile kernels of the full layout
+// (turnaround, reverse of a plain pass, of the first pass and of a junction)
+// run 256 threads of 32 amplitudes per vector: windows of 5 bits need fewer
+// exchanges per stage than the 4-bit windows of 512 threads (a 13-qubit stage
+// three instead of four windows, a 9- or 10-qubit stage two instead of
+// three), at 166-246 registers for two workgroups per CU.  Every other adjoint
+// kernel runs 512 threads (the complement-symmetric layout's two-bit factors
+// keep the 512-thread windows its stage code was checked for).
 int adjoint_thread_bits(int prec, const PassProg &pp, int turnaround)
 {
-    if (turnaround || prec != 0 || pp.pairs) return kAdjThreadBits;
+    if (prec != 0 || pp.pairs) return kAdjThreadBits;
     const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
-    return adjoint_variant(prec, pp, 0, mode) == kAdjOneJunc ? kAdjJuncThreadBits : kAdjThreadBits;
+    return adjoint_variant(prec, pp, turnaround, mode) == kAdjPersistent ? kAdjThreadBits : kAdjOneThreadBits;
 }
 
 // Grid of the kernel that launch_pass / launch_adjoint_pass pick for pp.

@@ -248,6 +248,7 @@ PassProg make_prog_raw(void *psi, int n, int prec, double *partials, const PassG
     pp.diag = cc.diag;
     pp.partials = partials;
     pp.ntiles = (int64_t)1 << (n - T);
+    pp.tb = tb;
     pp.n = n;
     pp.c = g.c;
     pp.q0 = g.q0;
@@ -572,9 +573,11 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     // turnaround: the last pass forward, lambda = C psi, the pass undone
     {
         const KSpec &k = ks.back();
-        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 1);
-        const int tb = adjoint_thread_bits(s->prec, pp, 1);
-        if (tb != kAdjThreadBits) pp = make_prog(s, geo[k.pass], k, cc, tb, 1);
+        // one-tile kernels run 256 threads (5-bit windows), the persistent
+        // kernel 512; the complement-symmetric layout keeps 512 threads (256
+        // measured no faster there)
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjOneThreadBits, 1);
+        if (s->sym || !adjoint_one_tile(s->prec, pp, 1)) pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 1);
         pp.lam = lam;
         if (qs_status st = launch_tiles(s, pp, 1, 1, QS_KIND_TURNAROUND, dim * (2.0 * ab + (pp.ctab ? 0.0 : 4.0)),
                                         &grid, where))
@@ -585,9 +588,8 @@ qs_status run_adjoint(qs_state s, const Circuit &cc, void *lam, const char *wher
     // reverse passes
     for (int i = (int)ks.size() - 2; i >= 0; --i) {
         const KSpec &k = ks[i];
-        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 2);
-        const int tb = adjoint_thread_bits(s->prec, pp, 0);
-        if (tb != kAdjThreadBits) pp = make_prog(s, geo[k.pass], k, cc, tb, 2);
+        PassProg pp = make_prog(s, geo[k.pass], k, cc, kAdjOneThreadBits, 2);
+        if (s->sym || !adjoint_one_tile(s->prec, pp, 0)) pp = make_prog(s, geo[k.pass], k, cc, kAdjThreadBits, 2);
         pp.lam = lam;
         pp.load_win = pp.final_win;
         if (ckpt) {

@@ -10,7 +10,7 @@ namespace qs {
 constexpr int kThreads = 256;         // threads per workgroup of the elementwise kernels
 constexpr int kFwdThreadBits = 8;     // forward tile kernels: 256 threads
 constexpr int kAdjThreadBits = 9;     // adjoint tile kernels: 512 threads (two vectors)
-constexpr int kAdjOneThreadBits = 8;  // ... but the complex64 one-tile kernels of the full layout: 256
+constexpr int kAdjOneThreadBits = 8;  // ... but the one-tile adjoint kernels: 256
 constexpr int kTileBitsC64 = 13;      // 8192 amplitudes (64 KiB) per tile, complex64
 constexpr int kTileBitsC128 = 12;     // 4096 amplitudes (64 KiB) per tile, complex128
 constexpr int kMaxWindows = 8;        // register windows per butterfly stage
@@ -63,6 +63,7 @@ struct PassProg {
     const int32_t *wts;   // weights recovered from the diagonal (layout kWt* below), when ctab is set
     double *partials;     // kSlots doubles per workgroup
     int64_t ntiles;       // 2^(n - T); workgroups loop over tiles
+    int tb;               // log2 threads of the kernel the window sequences are planned for
     int n, c, q0;
     uint32_t targets;     // mask of tile bits that are single-qubit gate targets
     uint32_t pairs;       // bit e: two-bit factor on tile bits e, e+1 (complement-symmetric storage)
@@ -199,9 +200,10 @@ __host__ __device__ __forceinline__ Addr win_addr(int tid, int s, int rb, int64_
 
 // Host-side launchers (one per kernel family); all return hipError_t.
 hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t st);
-// Threads (log2) of the reverse kernel (turnaround: 1) that launch_adjoint_pass
-// picks for pp; its windows must be planned for them.
-int adjoint_thread_bits(int prec, const PassProg &pp, int turnaround);
+// Whether launch_adjoint_pass runs pp (turnaround: 1), with its windows
+// planned for pp.tb threads, on a one-tile kernel rather than the persistent
+// 512-thread one.
+bool adjoint_one_tile(int prec, const PassProg &pp, int turnaround);
 // Bytes of the device buffer PassProg::tab points to (any precision).
 size_t pass_table_bytes();
 // Recover the weights of the cut function in diag (2^n entries, full layout)

@@ -405,29 +405,31 @@ void launch_adjoint_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st
 }
 
 // Adjoint kernel variants.  kAdjPersistent: the runtime-shape persistent
-// kernel with prefetch.  The others take one tile per workgroup and fit in
-// 128 registers without prefetch, so two workgroups share a CU: the
+// kernel with prefetch (512 threads).  The others take one tile per
+// workgroup, without prefetch, in the registers of two workgroups per CU: the
 // turnaround, a reverse pass of plain stages, the reverse of the first
 // forward pass (phase of layer 1, no writes) and the reverse junction (stage,
-// phase, stage; its diagonal is loaded at the phase point).  The turnaround
-// and the junction are one-tile for complex64 only: in complex128 they spill
-// at 128 registers.
+// phase, stage; its diagonal is loaded at the phase point).  They run 256
+// threads (pp.tb = 8: 5-bit windows, up to 256 registers); planned for 512
+// threads (128 registers) the complex128 turnaround and junction spill and
+// take the persistent kernel instead.
 enum { kAdjPersistent, kAdjOneTurn, kAdjOnePlain, kAdjOneFirst, kAdjOneJunc };
 
 int adjoint_variant(int prec, const PassProg &pp, int turnaround, int mode)
 {
     if (mode == kModeGeneral) return kAdjPersistent;
-    if (turnaround) return prec == 0 ? kAdjOneTurn : kAdjPersistent;
+    const bool spills = prec != 0 && pp.tb == kAdjThreadBits;
+    if (turnaround) return spills ? kAdjPersistent : kAdjOneTurn;
     switch (pass_shape(pp)) {
     case kShPost: return kAdjOnePlain;
     case kShInit | kShPhase | kShPost: return kAdjOneFirst;
-    case kShPre | kShPhase | kShPost: return prec == 0 ? kAdjOneJunc : kAdjPersistent;
+    case kShPre | kShPhase | kShPost: return spills ? kAdjPersistent : kAdjOneJunc;
     default: return kAdjPersistent;
     }
 }
 
-// AT: thread bits of the one-tile kernels (adjoint_thread_bits); the
-// persistent kernels are 512-thread only.
+// AT: thread bits of the one-tile kernels (pp.tb); the persistent kernels
+// are 512-thread only.
 template <int MODE, int AT>
 void launch_adjoint_m_at(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
@@ -460,10 +462,12 @@ void launch_adjoint_m_at(int prec, const PassProg &pp, int turnaround, int64_t g
 template <int MODE>
 void launch_adjoint_m(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
-    if (adjoint_thread_bits(prec, pp, turnaround) == kAdjOneThreadBits)
-        launch_adjoint_m_at<MODE, kAdjOneThreadBits>(prec, pp, turnaround, grid, st);
+    if (pp.tb == kAdjOneThreadBits) launch_adjoint_m_at<MODE, kAdjOneThreadBits>(prec, pp, turnaround, grid, st);
     else launch_adjoint_m_at<MODE, kAdjThreadBits>(prec, pp, turnaround, grid, st);
 }
+
+// Stage code path of an adjoint pass, for the threads its windows are planned for.
+int adjoint_mode(int prec, const PassProg &pp) { return tile_mode(pp, tile_bits(prec), pp.tb); }
 }  // namespace
 
 // Whether the kernel that launch_pass / launch_adjoint_pass pick for pp (kind
@@ -476,33 +480,27 @@ bool pass_takes_cut_table(int prec, const PassProg &pp, int kind)
     if (kind == 0) return pp.has_phase || pp.readout;
     if (kind == 1) return true;
     if (!pp.has_phase) return false;
-    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
-    return adjoint_variant(prec, pp, 0, mode) != kAdjOneJunc;
+    return adjoint_variant(prec, pp, 0, adjoint_mode(prec, pp)) != kAdjOneJunc;
 }
 
-// Threads (log2) of the adjoint kernel picked for pp, for which its windows
-// must be planned: the complex64 one-tile kernels of the full layout
-// (turnaround, reverse of a plain pass, of the first pass and of a junction)
-// run 256 threads of 32 amplitudes per vector: windows of 5 bits need fewer
-// exchanges per stage than the 4-bit windows of 512 threads (a 13-qubit stage
-// three instead of four windows, a 9- or 10-qubit stage two instead of
-// three), at 166-246 registers for two workgroups per CU.  Every other adjoint
-// kernel runs 512 threads (the complement-symmetric layout's two-bit factors
-// keep the 512-thread windows its stage code was checked for).
-int adjoint_thread_bits(int prec, const PassProg &pp, int turnaround)
+// The one-tile adjoint kernels run 256 threads of 32 amplitudes per vector
+// (complex64) or 16 (complex128): their windows of 5 (4) register bits need
+// fewer exchanges per stage than those of 512 threads (a 13-qubit stage three
+// windows instead of four, a 9- or 10-qubit stage two instead of three), at
+// 164-246 registers for two workgroups per CU; planned for 256 threads the
+// complex128 turnaround and junction fit too.  The host plans a pass for 256
+// threads first and falls back to 512 (the persistent kernel) when this
+// returns false.
+bool adjoint_one_tile(int prec, const PassProg &pp, int turnaround)
 {
-    if (prec != 0 || pp.pairs) return kAdjThreadBits;
-    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
-    return adjoint_variant(prec, pp, turnaround, mode) == kAdjPersistent ? kAdjThreadBits : kAdjOneThreadBits;
+    return adjoint_variant(prec, pp, turnaround, adjoint_mode(prec, pp)) != kAdjPersistent;
 }
 
 // Grid of the kernel that launch_pass / launch_adjoint_pass pick for pp.
 int64_t tile_grid(int prec, int adjoint, const PassProg &pp)
 {
     if (adjoint == 0) return pass_grid(prec, 0, pp.ntiles);
-    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
-    return adjoint_variant(prec, pp, adjoint == 1, mode) == kAdjPersistent ? pass_grid(prec, adjoint, pp.ntiles)
-                                                                            : pp.ntiles;
+    return adjoint_one_tile(prec, pp, adjoint == 1) ? pp.ntiles : pass_grid(prec, adjoint, pp.ntiles);
 }
 
 namespace {
@@ -560,13 +558,15 @@ hipError_t launch_pass(int prec, const PassProg &pp, int64_t grid, hipStream_t s
 
 hipError_t launch_adjoint_pass(int prec, const PassProg &pp, int turnaround, int64_t grid, hipStream_t st)
 {
-    const int mode = tile_mode(pp, tile_bits(prec), kAdjThreadBits);
+    // a program planned for 256 threads must take a one-tile kernel
+    if (pp.tb != kAdjThreadBits && (pp.tb != kAdjOneThreadBits || !adjoint_one_tile(prec, pp, turnaround)))
+        return hipErrorInvalidValue;
+    const int mode = adjoint_mode(prec, pp);
     // reverse passes in tangent form fold the stages' factors into the table
     // (see rev_tile)
     const bool fold = !turnaround && mode != kModeGeneral && !pp.init;
     if (hipError_t e = launch_phase_table(prec, pp, fold ? pp.factor : 1.0, st)) return e;
-    if (hipError_t e = launch_cut_table(prec, pp, turnaround ? 1 : 2, adjoint_thread_bits(prec, pp, turnaround), st))
-        return e;
+    if (hipError_t e = launch_cut_table(prec, pp, turnaround ? 1 : 2, pp.tb, st)) return e;
     switch (mode) {
     case kModeTan: launch_adjoint_m<kModeTan>(prec, pp, turnaround, grid, st); break;
     case kModeTanSym: launch_adjoint_m<kModeTanSym>(prec, pp, turnaround, grid, st); break;

@@ -3,10 +3,11 @@
 // tiles.h; these kernels copy the pass's phase table into LDS, walk tiles and
 // reduce the workgroup's partial sums.
 //
-// Forward passes launch one workgroup per tile.  The complex64 adjoint
-// kernels in tangent form do the same, two workgroups per CU; the others run
-// one persistent workgroup per CU that loads the next tile's vectors into
-// registers while it works on the current tile (see adjoint_variant).
+// Forward passes launch one workgroup per tile.  The adjoint kernels in
+// tangent form do the same, two workgroups per CU (256 threads in the full
+// layout); the others run one persistent workgroup per CU that loads the next
+// tile's vectors into registers while it works on the current tile (see
+// adjoint_variant).
 #include "plan.h"
 #include "tiles.h"
 

@@ -357,9 +357,11 @@ void launch_pass_k(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 }
 
 // Forward shapes with their own instantiation: the first pass (|+>, phase,
-// stage), a junction (stage, phase, stage) and the last pass (stage and
-// readout); anything else uses the runtime-shape kernel.  (A plain stage was
-// measured 1 ms slower fixed than with the runtime shape at n = 32.)
+// stage), a junction (stage, phase, stage), the last pass (stage and readout)
+// and, in tangent form, a plain stage with its compile-time tail (102-136
+// registers against 240 with runtime masks; bit-identical, a plain contiguous
+// pass ~0.1 ms faster at n = 32); anything else uses the runtime-shape
+// kernel.
 template <int MODE>
 void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
 {
@@ -370,6 +372,7 @@ void launch_pass_m(int prec, const PassProg &pp, int64_t grid, hipStream_t st)
         case kFirst: launch_pass_k<kFirst>(prec, pp, grid, st); return;
         case kJunc: launch_pass_k<kJunc>(prec, pp, grid, st); return;
         case kLast: launch_pass_k<kLast>(prec, pp, grid, st); return;
+        case kShPost: launch_pass_k<kShPost>(prec, pp, grid, st); return;
         default: launch_pass_s<MODE, -1>(prec, pp, grid, st); return;
         }
     }

@@ -381,6 +381,29 @@ __device__ __forceinline__ V scale_v(V a, typename Real<V>::T f)
     return V{a.x * f, a.y * f};
 }
 
+// Nontemporal (streaming) access to one amplitude: the load and the store
+// carry the streaming cache policy, as plain vector accesses of the element's
+// two components.
+template <typename V> struct NtVec;
+template <> struct NtVec<float2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct NtVec<double2> { typedef double T __attribute__((ext_vector_type(2))); };
+
+template <typename V>
+__device__ __forceinline__ V load_nt(const V *p)
+{
+    const typename NtVec<V>::T t = __builtin_nontemporal_load(reinterpret_cast<const typename NtVec<V>::T *>(p));
+    return V{t.x, t.y};
+}
+
+template <typename V>
+__device__ __forceinline__ void store_nt(V *p, V v)
+{
+    typename NtVec<V>::T t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<typename NtVec<V>::T *>(p));
+}
+
 // LDS byte offset of slot (thread part) XOR slot (register part).  The slot
 // map is linear over XOR, so the address of register r in a layout is the
 // thread's part XOR a part that depends only on r and the (uniform) window:

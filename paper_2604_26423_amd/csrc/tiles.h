@@ -422,6 +422,11 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     const int dwin = has_phase ? pp.phase_win : pp.final_win;
     const Geom g = geom_of(pp);
     const int64_t base = tile_base(tile, g.c, g.q0, g.m);
+    // A pass that only applies a stage streams the state with nontemporal
+    // loads and stores (measured: plain passes 9% faster, the n = 32 forward
+    // 4%, the complex128 one 12%); with them the passes that apply a phase or
+    // read out ran up to 14% slower, so those keep ordinary accesses.
+    const bool stream = !has_phase && !readout;
     V v[NR];
     int32_t dg[NR];
     // C_t first, so that the latency of its loads overlaps stage A
@@ -430,6 +435,8 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     if (init) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) v[r] = V{(R)pp.amp0, (R)0};
+    } else if (stream) {
+        for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = load_nt(&psi[x]); });
     } else {
         for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { v[r] = psi[x]; });
     }
@@ -458,7 +465,10 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
             acc[1] += pr * (double)dg[r];
         }
     }
-    for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { out[x] = v[r]; });
+    if (stream)
+        for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { store_nt(&out[x], v[r]); });
+    else
+        for_each_reg<NR>(win_addr(tid, cur, RB, base, g.c, g.q0), [&](int r, int64_t x) { out[x] = v[r]; });
 }
 
 // Turnaround on one tile: apply the last forward pass, read out the norm and

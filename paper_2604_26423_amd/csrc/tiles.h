@@ -424,7 +424,7 @@ __device__ __forceinline__ void fwd_tile(const PassProg &pp, int64_t tile, V *ld
     const int64_t base = tile_base(tile, g.c, g.q0, g.m);
     // A pass of the full layout that only applies a stage streams the state
     // with nontemporal loads and stores (measured: plain passes 9% faster, the
-    // n = 32 forward 4%, the complex128 one 12%).  The passes that apply a
+    // n = 32 forward 4%, the complex128 one 4-12%).  The passes that apply a
     // phase or read out ran up to 14% slower with them, and the
     // complement-symmetric layout (two-bit factors) 6% slower, so those keep
     // ordinary accesses.
